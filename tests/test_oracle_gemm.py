@@ -1,0 +1,277 @@
+"""Pins of the oracle's projected GEMM against facts fixed by the paper and by
+mathematics (none of them re-types the oracle's own loops).
+
+Paper: Sec. III-A eq. (5)-(8) (projection identity, partial sums),
+Sec. III-B eq. (15) (block-diagonal projection), eq. (14) (DC-only case).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_2860_amd import inputs
+
+
+def _rand(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def _orthonormal_dct(L):
+    """Textbook orthonormal DCT-II (columns = basis vectors), built here from
+    the cosine formula with the standard scale factors."""
+    t = np.arange(L)[:, None]
+    j = np.arange(L)[None, :]
+    C = np.cos(np.pi / L * (t + 0.5) * j)
+    C[:, 0] *= np.sqrt(1.0 / L)
+    C[:, 1:] *= np.sqrt(2.0 / L)
+    return C
+
+
+# --------------------------------------------------------------- bases
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 8, 16, 64])
+def test_dct_inverse_matches_textbook(L):
+    """The unnormalised DCT-II of eq. (7) has the textbook inverse
+    D = diag(1/L, 2/L, ..., 2/L) C^T (cosine orthogonality)."""
+    C = oracle.basis_dct2(L)
+    scale = np.full(L, 2.0 / L)
+    scale[0] = 1.0 / L
+    D_textbook = scale[:, None] * C.T
+    np.testing.assert_allclose(oracle.invert(C), D_textbook, atol=1e-12)
+    # spot values of eq. (7)
+    assert C[0, 0] == 1.0
+    if L > 1:
+        assert abs(C[0, 1] - np.cos(np.pi / (2 * L))) < 1e-15
+
+
+@pytest.mark.parametrize("L", [1, 2, 4, 8, 16])
+def test_haar_columns_orthogonal_and_l2_equals_dct(L):
+    H = oracle.basis_haar(L)
+    G = H.T @ H
+    np.testing.assert_allclose(G, np.diag(np.diag(G)), atol=0)      # orthogonal columns
+    assert np.all(H[:, 0] == 1.0)                                    # scaling function first
+    np.testing.assert_allclose(oracle.invert(H) @ H, np.eye(L), atol=1e-13)
+    if L == 2:   # L = 2 Haar and DCT-II differ only by column scaling
+        C = oracle.basis_dct2(2)
+        np.testing.assert_allclose(H[:, 1] * C[0, 1], C[:, 1], atol=1e-15)
+
+
+def test_haar_rejects_non_power_of_two():
+    with pytest.raises(RuntimeError):
+        oracle.basis_haar(6)
+
+
+def test_invert_random_and_singular():
+    C = _rand((7, 7), 3)
+    np.testing.assert_allclose(oracle.invert(C) @ C, np.eye(7), atol=1e-12)
+    S = C.copy()
+    S[:, 3] = S[:, 1] * 2.0
+    S[:, 3] = 0.0
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.invert(S)
+
+
+# ------------------------------------------------------------ exactness
+
+@pytest.mark.parametrize("kind", ["dct2", "haar", "identity", "random"])
+@pytest.mark.parametrize("M,K,W,L", [(5, 32, 7, 8), (9, 37, 4, 4), (16, 256, 16, 16), (3, 10, 3, 16)])
+def test_full_r_is_exact_gemm(kind, M, K, W, L):
+    """eq. (6): with all L projections the projected product equals A B."""
+    if kind == "random":
+        C = _rand((L, L), 11) + 3 * np.eye(L)
+        D = oracle.invert(C)
+    else:
+        C, D = oracle.basis(kind, L)
+    A, B = _rand((M, K), 1), _rand((K, W), 2)
+    ref = np.matmul(A, B)
+    got = oracle.gemm_proj(A, B, C, D, L)
+    assert oracle.rel_fro(got, ref) < 1e-12
+    np.testing.assert_allclose(oracle.gemm(A, B), ref, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------- brute force eq. (15)
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 8])
+def test_brute_force_block_diagonal_every_r(L):
+    """Explicit C_N, S_r, D_N (eq. (15)) on tiny shapes, every r, including a
+    contraction length that is not a multiple of L (zero extension)."""
+    C = _rand((L, L), 100 + L) + 2 * np.eye(L)
+    D = oracle.invert(C)
+    for K in sorted({L, 3 * L, 3 * L + 1}):
+        A, B = _rand((3, K), K), _rand((K, 2), K + 1)
+        for r in range(1, L + 1):
+            brute = oracle.gemm_proj_brute(A, B, C, D, r)
+            got = oracle.gemm_proj(A, B, C, D, r)
+            np.testing.assert_allclose(got, brute, rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("kind", ["dct2", "haar"])
+def test_pipeline_equals_closed_form_every_r(kind):
+    L = 8
+    C, D = oracle.basis(kind, L)
+    A, B = _rand((11, 45), 5), _rand((45, 13), 6)
+    for r in range(1, L + 1):
+        np.testing.assert_allclose(oracle.gemm_proj(A, B, C, D, r), oracle.gemm_proj_closed(A, B, C, D, r),
+                                   rtol=1e-11, atol=1e-11)
+
+
+# ------------------------------------------------------ special cases
+
+@pytest.mark.parametrize("kind", ["dct2", "haar"])
+@pytest.mark.parametrize("K", [32, 35])
+def test_dc_only_case(kind, K):
+    """eq. (14): with one projection of the DCT (or Haar), the result keeps the
+    block DC terms: R1[i, w] = sum_j (sum_t A[i, jL+t]) * mean_u B[jL+u, w]
+    (blocks zero-extended to L)."""
+    L = 8
+    C, D = oracle.basis(kind, L)
+    A, B = _rand((4, K), 7), _rand((K, 5), 8)
+    G = -(-K // L)
+    Ap = np.zeros((4, G * L)); Ap[:, :K] = A
+    Bp = np.zeros((G * L, 5)); Bp[:K] = B
+    sums = Ap.reshape(4, G, L).sum(axis=2)
+    means = Bp.reshape(G, L, 5).mean(axis=1)
+    expect = sums @ means
+    np.testing.assert_allclose(oracle.gemm_proj(A, B, C, D, 1), expect, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 5])
+def test_identity_basis_is_column_subsampling(r):
+    """With C = I the first r projections keep the contraction indices
+    k with (k mod L) < r."""
+    L = 5
+    C, D = oracle.basis("identity", L)
+    A, B = _rand((6, 23), 9), _rand((23, 4), 10)
+    keep = np.array([k for k in range(23) if k % L < r])
+    np.testing.assert_allclose(oracle.gemm_proj(A, B, C, D, r), A[:, keep] @ B[keep, :], rtol=1e-12, atol=1e-12)
+
+
+def test_column_scaling_invariance_paper_dct_vs_orthonormal():
+    """Scaling the columns of C (and the rows of D inversely) leaves every
+    partial sum unchanged: the paper's unnormalised DCT-II and the
+    orthonormal DCT-II give the same projected GEMM."""
+    L = 16
+    Cp, Dp = oracle.basis("dct2", L)
+    Co = _orthonormal_dct(L)
+    Do = Co.T
+    A, B = _rand((7, 64), 12), _rand((64, 9), 13)
+    for r in (1, 3, 8, 16):
+        np.testing.assert_allclose(oracle.gemm_proj(A, B, Cp, Dp, r), oracle.gemm_proj(A, B, Co, Do, r),
+                                   rtol=1e-11, atol=1e-11)
+
+
+def test_increment_is_one_projection_product_and_linearity():
+    """eq. (8): R_{r+1} - R_r equals the product of the r-th projected blocks;
+    the projected GEMM is linear in A and in B."""
+    L = 8
+    C, D = oracle.basis("dct2", L)
+    A, B = _rand((6, 40), 14), _rand((40, 7), 15)
+    Ac = oracle.project_a(A, C, L)
+    Bd = oracle.project_b(B, D, L)
+    for r in range(1, L):
+        inc = oracle.gemm_proj(A, B, C, D, r + 1) - oracle.gemm_proj(A, B, C, D, r)
+        np.testing.assert_allclose(inc, Ac[r] @ Bd[r], rtol=1e-10, atol=1e-10)
+    A2 = _rand((6, 40), 16)
+    np.testing.assert_allclose(oracle.gemm_proj(2 * A - A2, B, C, D, 3),
+                               2 * oracle.gemm_proj(A, B, C, D, 3) - oracle.gemm_proj(A2, B, C, D, 3),
+                               rtol=1e-10, atol=1e-10)
+
+
+def test_projected_block_shapes_match_paper_example():
+    """Sec. III-B: with N = 144 and L = 8 the projected product is
+    144 x 18 by 18 x 144."""
+    C, D = oracle.basis("dct2", 8)
+    A = _rand((144, 144), 17)
+    assert oracle.project_a(A, C, 1).shape == (1, 144, 18)
+    assert oracle.project_b(A, D, 1).shape == (1, 18, 144)
+
+
+def test_block_subset_matches_full():
+    C, D = oracle.basis("dct2", 16)
+    A, B = _rand((20, 70), 18), _rand((70, 30), 19)
+    rows, cols = [0, 5, 19], [1, 2, 29, 7]
+    for r in (1, 5, 16):
+        full = oracle.gemm_proj(A, B, C, D, r)
+        np.testing.assert_allclose(oracle.gemm_proj_block(A, B, C, D, r, rows, cols),
+                                   full[np.ix_(rows, cols)], rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------ error behaviour in r
+
+def test_residuals_nonincreasing_orthonormal():
+    """For an orthonormal basis, Q_r is an orthogonal projector onto a growing
+    subspace, so ||A (I - Q_{r,K})||_F is non-increasing in r.  The
+    unnormalised DCT gives the same Q_r (column-scaling invariance)."""
+    L = 16
+    C, D = oracle.basis("dct2", L)
+    A = inputs.smoothed_field(32, 128, sigma=4.0, seed=20)
+    I = np.eye(L)
+    prev = np.inf
+    for r in range(1, L + 1):
+        G = 128 // L
+        res = A - A @ oracle.blockdiag(oracle.q_matrix(C, D, r), G)
+        # the residual is what the projected GEMM against I leaves out
+        np.testing.assert_allclose(A @ oracle.blockdiag(oracle.q_matrix(C, D, r), G),
+                                   oracle.gemm_proj(A, np.eye(128), C, D, r), rtol=1e-10, atol=1e-9)
+        n = np.linalg.norm(res)
+        assert n <= prev * (1 + 1e-12) + 1e-9
+        prev = n
+    assert prev < 1e-9 * np.linalg.norm(A) and I.shape == (L, L)
+
+
+def test_gram_case_error_nonincreasing():
+    """B = A^T: the error A (I - Q) A^T is positive semidefinite and shrinks in
+    the Loewner order as r grows, so its Frobenius norm is non-increasing."""
+    L = 8
+    C, D = oracle.basis("dct2", L)
+    A = inputs.smoothed_field(24, 64, sigma=3.0, seed=21)
+    exact = A @ A.T
+    errs = [np.linalg.norm(exact - oracle.gemm_proj(A, A.T, C, D, r)) for r in range(1, L + 1)]
+    assert all(b <= a * (1 + 1e-12) + 1e-9 for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-9 * np.linalg.norm(exact)
+
+
+def test_error_not_monotone_in_general():
+    """A reading of 'graceful degradation' as a theorem fails for general
+    A, B: with orthonormal DCT-4 coefficients a_c = (0,1,1,0) and
+    b_d = (0,1,-1,0) the partial sums are 0, 1, 0, 0 while a.b = 0, so the
+    error for r = 1..4 is 0, 1, 0, 0."""
+    C, D = oracle.basis("dct2", 4)
+    Co = _orthonormal_dct(4)
+    a = (np.array([0.0, 1.0, 1.0, 0.0]) @ Co.T)[None, :]      # a C = a_c
+    b = (Co @ np.array([0.0, 1.0, -1.0, 0.0]))[:, None]       # C^T b = b_d
+    errs = [abs(float(oracle.gemm_proj(a, b, C, D, r)[0, 0])) for r in range(1, 5)]
+    np.testing.assert_allclose(errs, [0.0, 1.0, 0.0, 0.0], atol=1e-12)
+
+
+# ------------------------------------------------------------- gradients
+
+@pytest.mark.parametrize("r", [1, 3, 8])
+def test_gradient_matches_central_differences(r):
+    L = 8
+    C, D = oracle.basis("dct2", L)
+    A, B = _rand((3, 12), 22), _rand((12, 4), 23)
+    dR = _rand((3, 4), 24)
+    dA, dB = oracle.gemm_proj_grad(A, B, C, D, r, dR)
+    h = 1e-6
+
+    def f(A_, B_):
+        return float(np.sum(oracle.gemm_proj(A_, B_, C, D, r) * dR))
+
+    for (i, k) in itertools.product(range(3), range(12)):
+        E = np.zeros_like(A); E[i, k] = h
+        assert abs((f(A + E, B) - f(A - E, B)) / (2 * h) - dA[i, k]) < 1e-7
+    for (k, w) in itertools.product(range(12), range(4)):
+        E = np.zeros_like(B); E[k, w] = h
+        assert abs((f(A, B + E) - f(A, B - E)) / (2 * h) - dB[k, w]) < 1e-7
+
+
+def test_gradient_full_r_is_exact_gradient():
+    L = 4
+    C, D = oracle.basis("haar", L)
+    A, B = _rand((5, 10), 25), _rand((10, 6), 26)
+    dR = _rand((5, 6), 27)
+    dA, dB = oracle.gemm_proj_grad(A, B, C, D, L, dR)
+    np.testing.assert_allclose(dA, dR @ B.T, rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(dB, A.T @ dR, rtol=1e-11, atol=1e-11)
