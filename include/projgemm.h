@@ -1,0 +1,183 @@
+/*
+ * projgemm.h -- C ABI of libprojgemm.so: projection-based precision-scalable
+ * GEMM and 1-D cross-correlation / convolution on AMD MI355X (gfx950).
+ *
+ * Method: Anam, Whatmough, Andreopoulos, "Precision-Energy-Throughput
+ * Scaling of Generic Matrix Multiplication and Convolution Kernels via
+ * Linear Projections", IEEE TCSVT 24(11), 2014 (arXiv:1411.2860).
+ *
+ * Notation (paper Sec. III, Table I):
+ *   A is M x K, B is K x W, R = A B is M x W.  The contraction index k is
+ *   split into G = ceil(K / L) groups of L consecutive indices starting at
+ *   0 (the block-diagonal C_N, D_N of eq. (15)); indices past K are treated
+ *   as zeros.  C is the L x L projection matrix, column l being projection
+ *   l (a_c = a C, eq. (5)); D = C^{-1} projects the B side (b_d = D b).
+ *   r is the NUMBER of projections kept, 1 <= r <= L (the paper counts them
+ *   as l + 1, 0 <= l < L).  With r = L the result is exact (eq. (6)); with
+ *   r < L it is the partial sum of eq. (8):
+ *       R_hat = sum_{l<r} A_c^{(l)} B_d^{(l)} = A Q_{r,K} B,
+ *       Q_{r,K} = blockdiag(C[:, :r] D[:r, :]).
+ *
+ * Conventions of every entry point:
+ *   - Matrices are row-major with a leading dimension (in elements).
+ *   - Tensors and workspaces are device memory owned by the caller; the
+ *     library keeps no pointer to them after the call.  Calls allocate no
+ *     device memory: scratch comes from the caller's workspace, whose size
+ *     the matching *_workspace_bytes query returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously; no call synchronises the stream.
+ *   - Every argument check runs on the host before any device work, so an
+ *     invalid call returns an error code and touches no device state.
+ *     Errors are returned, never raised or aborted on.
+ */
+#ifndef PROJGEMM_H
+#define PROJGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PJ_OK = 0,
+    PJ_ERR_ARG = -1,          /* null pointer, bad enum, r or L out of range   */
+    PJ_ERR_SHAPE = -2,        /* non-positive size, leading dimension too small */
+    PJ_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement    */
+    PJ_ERR_WORKSPACE = -4,    /* workspace missing or smaller than the query    */
+    PJ_ERR_SINGULAR = -5,     /* custom projection matrix is not invertible     */
+    PJ_ERR_HIP = -6           /* a HIP runtime call or kernel launch failed     */
+} pj_status;
+
+typedef enum {
+    PJ_BASIS_DCT2 = 0,        /* DCT-II, eq. (7); stored orthonormal (see below) */
+    PJ_BASIS_HAAR = 1,        /* Haar decomposition basis; L a power of two      */
+    PJ_BASIS_IDENTITY = 2,    /* C = I: keeps indices k with (k mod L) < r       */
+    PJ_BASIS_CUSTOM = 3       /* any invertible C given by the caller            */
+} pj_basis_kind;
+
+/* Arithmetic of the reduced contraction.  Inputs and outputs are FP64 for
+ * PJ_F64 and FP32 for every other mode; projections are computed in FP32
+ * (FP64 for PJ_F64) and rounded to the mode's operand format.
+ *   PJ_BF16 / PJ_F16   : one rounded operand, FP32 accumulation;
+ *   PJ_BF16X3 / PJ_F16X3: x = hi + lo split, R = hi*hi + hi*lo + lo*hi,
+ *                         FP32 accumulation (about FP32-level error);
+ *   PJ_FP8             : OCP FP8 e4m3 operands with one power-of-two (E8M0)
+ *                         scale per 32 consecutive contraction indices,
+ *                         FP32 accumulation; r <= 8 only;
+ *   PJ_FP8X2           : FP8 hi + lo split, three products; r <= 8 only. */
+typedef enum {
+    PJ_F64 = 0, PJ_F32 = 1, PJ_BF16 = 2, PJ_BF16X3 = 3,
+    PJ_F16 = 4, PJ_F16X3 = 5, PJ_FP8 = 6, PJ_FP8X2 = 7
+} pj_precision;
+
+typedef enum { PJ_XCORR = 0, PJ_CONV = 1 } pj_conv_mode;
+
+typedef struct pj_basis_s* pj_basis;
+
+/* Human-readable name of a status code (static string). */
+const char* pj_status_str(int status);
+
+/* ------------------------------------------------------------------ basis */
+
+/* Builds the L x L projection matrix C of the given kind and D = C^{-1}
+ * (paper eq. (5)-(7); Haar: Sec. IV-A / V-B), in FP64 on the host, and
+ * uploads FP32 and FP64 copies to the current device (synchronously).
+ *   kind  : PJ_BASIS_*.  DCT-II is stored orthonormal (column j scaled by
+ *           sqrt(1/L) for j = 0, sqrt(2/L) otherwise) with D = C^T: the
+ *           projected result does not depend on the scale of the columns of
+ *           C, so this equals eq. (7)'s unnormalised matrix.  Haar is the
+ *           orthonormal Haar basis with column 0 the scaling function, then
+ *           wavelets from coarse to fine scale, shifts ascending.
+ *   L     : 1 <= L <= 256 (Haar: a power of two).
+ *   C     : row-major L x L (C[t*L + l]) for PJ_BASIS_CUSTOM, else NULL.
+ *           D is found by LU with partial pivoting; PJ_ERR_SINGULAR if a
+ *           pivot is below 1e-12 times the largest |C| entry.
+ * The basis is immutable and may be shared by concurrent calls.  If no
+ * device is present the host copy is still built and device calls using it
+ * return PJ_ERR_HIP. */
+int pj_basis_create(pj_basis* out, int kind, int L, const double* C);
+
+/* FP64 copies of C and D (row-major L x L each); either pointer may be NULL. */
+int pj_basis_get(pj_basis b, double* C_out, double* D_out);
+
+/* L of the basis, or a negative status. */
+int pj_basis_L(pj_basis b);
+
+int pj_basis_destroy(pj_basis b);
+
+/* --------------------------------------------------------- projected GEMM */
+
+/* Bytes of workspace proj_gemm needs (0 for invalid arguments). */
+size_t pj_gemm_workspace_bytes(int M, int W, int K, int L, int r, int prec);
+
+/* R <- A Q_{r,K} B + beta R  (paper Sec. III-A/B, eq. (5)-(8), (15)).
+ *   transA = 'N': A is M x K (element (i,k) at A[i*lda + k]);
+ *            'T': A is stored K x M (element (i,k) at A[k*lda + i]).
+ *   transB = 'N': B is K x W (element (k,w) at B[k*ldb + w]);
+ *            'T': B is stored W x K (element (k,w) at B[w*ldb + k]).
+ *   R is M x W, element (i,w) at R[i*ldr + w]; beta = 0 never reads R.
+ *   A, B, R are double for PJ_F64 and float otherwise.
+ * Steps (all on `stream`): project-and-pack A (Sec. III-B, rows of A times
+ * columns of C), project-and-pack B (columns of B times rows of D), one
+ * MFMA contraction over r*G projected indices accumulating all r partial
+ * products (eq. (8)).  Requires ws_bytes >= pj_gemm_workspace_bytes(...). */
+int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K,
+              const void* A, int64_t lda, const void* B, int64_t ldb,
+              float beta, void* R, int64_t ldr, int prec,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* ---- the same path in separate steps (a static B packed once, r sweeps) --
+ * A packed operand holds `rows` rows of a matrix projected onto the first
+ * rmax projections, in the MFMA fragment order of `prec` (opaque layout).
+ * A buffer packed at rmax serves every r <= rmax in pj_gemm_packed. */
+
+/* Bytes of one packed operand with `rows` rows and contraction length K. */
+size_t pj_packed_bytes(int rows, int K, int L, int rmax, int prec);
+
+/* Packs the A side: rows i < M of A (layout as proj_gemm's transA),
+ * projected with the columns of C (A_c = A C_N, eq. (5), (15)). */
+int pj_pack_a(pj_basis b, int rmax, char transA, int M, int K, const void* A, int64_t lda,
+              int prec, void* packed, size_t packed_bytes, void* stream);
+
+/* Packs the B side: columns w < W of B (layout as proj_gemm's transB),
+ * projected with the rows of D (B_d = D_N B, eq. (5), (15)). */
+int pj_pack_b(pj_basis b, int rmax, char transB, int W, int K, const void* B, int64_t ldb,
+              int prec, void* packed, size_t packed_bytes, void* stream);
+
+/* R <- sum_{l<r} A_c^{(l)} B_d^{(l)} + beta R from operands packed with the
+ * same (K, L, prec) at rmax_a >= r and rmax_b >= r; a_bytes and b_bytes are
+ * the sizes of the two buffers (PJ_ERR_WORKSPACE if smaller than
+ * pj_packed_bytes for their rmax). */
+int pj_gemm_packed(int r, int M, int W, int K, int L, int prec,
+                   const void* Ap, int rmax_a, size_t a_bytes,
+                   const void* Bp, int rmax_b, size_t b_bytes,
+                   float beta, void* R, int64_t ldr, void* stream);
+
+/* ------------------------------------------- projected cross-correlation */
+
+/* Bytes of workspace proj_conv1d needs (0 for invalid arguments). */
+size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec);
+
+/* Valid cross-correlation (mode PJ_XCORR) or convolution (PJ_CONV) of the
+ * signal s (W samples) with the kernel k (N samples, 1 <= N <= W), computed on
+ * the first r projections (paper Sec. II-B eq. (3); Sec. III-A eq. (10)-(14);
+ * Sec. III-B, projection during the blocking of the input):
+ *   XCORR: y[m] = sum_{n<N} k[n]       s_r[m + n],  m = 0 .. W - N
+ *   CONV : y[m] = sum_{n<N} k[N-1-n]   s_r[m + n]
+ * where s_r is s with every aligned block of L samples (zero-extended past W)
+ * replaced by its reconstruction from the first r projections,
+ * s_r|block = s|block C[:, :r] D[:r, :].  Equivalently the signal blocks are
+ * projected with C, the kernel is projected with D at each of the L phases,
+ * and each output accumulates r products (exact at r = L).
+ *   s, k, y : device float arrays (y has W - N + 1 elements).
+ *   prec    : PJ_F32 (FP32 projections, FP32 matrix-core accumulation).
+ * Requires ws_bytes >= pj_conv1d_workspace_bytes(...). */
+int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k,
+                float* y, int prec, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROJGEMM_H */

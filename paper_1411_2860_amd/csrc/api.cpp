@@ -1,0 +1,387 @@
+// api.cpp -- the C ABI of libprojgemm (include/projgemm.h): FP64 basis
+// construction on the host, argument validation (always before any device
+// work), workspace carving and kernel launches.
+#include "../../include/projgemm.h"
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+using namespace pj;
+
+struct pj_basis_s {
+    int kind;
+    int L;
+    std::vector<double> C, D;        // FP64 host copies, row-major L x L
+    bool on_device = false;
+    int device = -1;
+    float* Cf = nullptr;             // C[t][l]           (A side coefficients)
+    float* DTf = nullptr;            // D^T[t][l] = D[l][t] (B side coefficients)
+    double* Cd = nullptr;
+    double* DTd = nullptr;
+};
+
+namespace {
+
+constexpr int kMaxL = 256;
+
+bool valid_prec(int p) { return p >= PJ_F64 && p <= PJ_FP8X2; }
+bool implemented_prec(int p) { return p >= PJ_F64 && p <= PJ_F16X3; }
+bool is_n(char t) { return t == 'N' || t == 'n'; }
+bool is_t(char t) { return t == 'T' || t == 't'; }
+
+// Orthonormal DCT-II: C[t][l] = a_l cos(pi/L (t + 1/2) l), a_0 = sqrt(1/L),
+// a_l = sqrt(2/L); columns are the basis vectors of eq. (7), rescaled.
+void make_dct2(int L, std::vector<double>& C)
+{
+    const double pi = 3.14159265358979323846;
+    for (int t = 0; t < L; ++t)
+        for (int l = 0; l < L; ++l) {
+            double a = (l == 0) ? std::sqrt(1.0 / L) : std::sqrt(2.0 / L);
+            C[(size_t)t * L + l] = a * std::cos(pi / L * (t + 0.5) * l);
+        }
+}
+
+// Orthonormal Haar: column 0 the scaling function, then for each scale from
+// coarse to fine the shifted wavelets (+ on the first half of the support,
+// - on the second), each normalised to unit length.
+void make_haar(int L, std::vector<double>& C)
+{
+    std::fill(C.begin(), C.end(), 0.0);
+    for (int t = 0; t < L; ++t) C[(size_t)t * L] = 1.0 / std::sqrt((double)L);
+    int col = 1;
+    for (int count = 1; count < L; count *= 2) {
+        const int len = L / count;
+        const double v = 1.0 / std::sqrt((double)len);
+        for (int p = 0; p < count; ++p, ++col)
+            for (int t = 0; t < len; ++t) C[(size_t)(p * len + t) * L + col] = (t < len / 2) ? v : -v;
+    }
+}
+
+// D = C^{-1} by LU with partial pivoting; false if C is (numerically) singular.
+bool invert_lu(int L, const std::vector<double>& C, std::vector<double>& D)
+{
+    std::vector<double> a(C);
+    std::vector<int> piv(L);
+    double amax = 0.0;
+    for (double v : C) amax = std::fmax(amax, std::fabs(v));
+    if (!(amax > 0.0) || !std::isfinite(amax)) return false;
+    for (int k = 0; k < L; ++k) {
+        int p = k;
+        for (int i = k + 1; i < L; ++i)
+            if (std::fabs(a[(size_t)i * L + k]) > std::fabs(a[(size_t)p * L + k])) p = i;
+        if (std::fabs(a[(size_t)p * L + k]) <= 1e-12 * amax) return false;
+        piv[k] = p;
+        if (p != k)
+            for (int j = 0; j < L; ++j) std::swap(a[(size_t)k * L + j], a[(size_t)p * L + j]);
+        for (int i = k + 1; i < L; ++i) {
+            a[(size_t)i * L + k] /= a[(size_t)k * L + k];
+            const double f = a[(size_t)i * L + k];
+            for (int j = k + 1; j < L; ++j) a[(size_t)i * L + j] -= f * a[(size_t)k * L + j];
+        }
+    }
+    // solve A X = I column by column (rows of the identity permuted as P)
+    for (int c = 0; c < L; ++c) {
+        std::vector<double> x(L, 0.0);
+        x[c] = 1.0;
+        for (int k = 0; k < L; ++k)
+            if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+        for (int i = 0; i < L; ++i)
+            for (int j = 0; j < i; ++j) x[i] -= a[(size_t)i * L + j] * x[j];
+        for (int i = L - 1; i >= 0; --i) {
+            for (int j = i + 1; j < L; ++j) x[i] -= a[(size_t)i * L + j] * x[j];
+            x[i] /= a[(size_t)i * L + i];
+        }
+        for (int i = 0; i < L; ++i) D[(size_t)i * L + c] = x[i];
+    }
+    return true;
+}
+
+void free_device(pj_basis b)
+{
+    if (!b->on_device) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(b->device);
+    (void)hipFree(b->Cf);
+    (void)hipFree(b->DTf);
+    (void)hipFree(b->Cd);
+    (void)hipFree(b->DTd);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    b->on_device = false;
+}
+
+bool upload(pj_basis b)
+{
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (hipGetDevice(&b->device) != hipSuccess) return false;
+    const int L = b->L;
+    const size_t n = (size_t)L * L;
+    std::vector<float> cf(n), dtf(n);
+    std::vector<double> dtd(n);
+    for (int t = 0; t < L; ++t)
+        for (int l = 0; l < L; ++l) {
+            cf[(size_t)t * L + l] = (float)b->C[(size_t)t * L + l];
+            dtd[(size_t)t * L + l] = b->D[(size_t)l * L + t];
+            dtf[(size_t)t * L + l] = (float)b->D[(size_t)l * L + t];
+        }
+    bool ok = hipMalloc((void**)&b->Cf, n * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&b->DTf, n * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&b->Cd, n * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&b->DTd, n * sizeof(double)) == hipSuccess &&
+              hipMemcpy(b->Cf, cf.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(b->DTf, dtf.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(b->Cd, b->C.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(b->DTd, dtd.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    b->on_device = true;   // so that free_device releases partial allocations
+    if (!ok) {
+        free_device(b);
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+// Common checks of one packed operand request.
+int check_pack(pj_basis b, int rmax, char trans, int rows, int K, const void* X, int64_t ld, int prec,
+               const void* packed, size_t packed_bytes)
+{
+    if (!b || !X || !packed) return PJ_ERR_ARG;
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    if (rmax < 1 || rmax > b->L) return PJ_ERR_ARG;
+    if (!is_n(trans) && !is_t(trans)) return PJ_ERR_ARG;
+    if (rows < 1 || K < 1) return PJ_ERR_SHAPE;
+    if (ld < (is_n(trans) ? (int64_t)K : (int64_t)rows)) return PJ_ERR_SHAPE;
+    if ((prec == PJ_FP8 || prec == PJ_FP8X2) && rmax > 8) return PJ_ERR_UNSUPPORTED;
+    if (!implemented_prec(prec)) return PJ_ERR_UNSUPPORTED;
+    if (packed_bytes < (size_t)pack_geom(rows, K, b->L, rmax, prec).total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    return PJ_OK;
+}
+
+int do_pack(pj_basis b, int rmax, bool a_side, char trans, int rows, int K, const void* X, int64_t ld,
+            int prec, void* packed, void* stream)
+{
+    PackArgs a;
+    a.X = X;
+    a.ld = ld;
+    // A side: rows of A are rows (trans 'N' = k contiguous).  B side: the rows
+    // of the packed operand are the columns of B, so 'N' (B is K x W) is the
+    // strided case and 'T' (B stored W x K) the contiguous one.
+    a.trans = a_side ? (is_t(trans) ? 1 : 0) : (is_n(trans) ? 1 : 0);
+    a.P = rows;
+    a.K = K;
+    a.L = b->L;
+    a.r = rmax;
+    if (prec == PJ_F64) a.coef = a_side ? (const void*)b->Cd : (const void*)b->DTd;
+    else a.coef = a_side ? (const void*)b->Cf : (const void*)b->DTf;
+    a.out = packed;
+    a.geom = pack_geom(rows, K, b->L, rmax, prec);
+    if (a.geom.Gp / layout_of(prec).KB > 65535 || a.geom.nrb > 0x7fffffff) return PJ_ERR_UNSUPPORTED;
+    int rc = launch_pack(prec, a, (hipStream_t)stream);
+    return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+const char* pj_status_str(int s)
+{
+    switch (s) {
+    case PJ_OK: return "ok";
+    case PJ_ERR_ARG: return "invalid argument";
+    case PJ_ERR_SHAPE: return "invalid shape or leading dimension";
+    case PJ_ERR_UNSUPPORTED: return "unsupported request";
+    case PJ_ERR_WORKSPACE: return "workspace missing or too small";
+    case PJ_ERR_SINGULAR: return "projection matrix is singular";
+    case PJ_ERR_HIP: return "HIP runtime or launch failure";
+    default: return "unknown status";
+    }
+}
+
+int pj_basis_create(pj_basis* out, int kind, int L, const double* C)
+{
+    if (!out) return PJ_ERR_ARG;
+    *out = nullptr;
+    if (L < 1 || L > kMaxL) return PJ_ERR_ARG;
+    if (kind < PJ_BASIS_DCT2 || kind > PJ_BASIS_CUSTOM) return PJ_ERR_ARG;
+    if (kind == PJ_BASIS_CUSTOM && !C) return PJ_ERR_ARG;
+    if (kind != PJ_BASIS_CUSTOM && C) return PJ_ERR_ARG;
+    if (kind == PJ_BASIS_HAAR && (L & (L - 1)) != 0) return PJ_ERR_ARG;
+    pj_basis b = new (std::nothrow) pj_basis_s;
+    if (!b) return PJ_ERR_ARG;
+    b->kind = kind;
+    b->L = L;
+    const size_t n = (size_t)L * L;
+    b->C.assign(n, 0.0);
+    b->D.assign(n, 0.0);
+    switch (kind) {
+    case PJ_BASIS_DCT2: make_dct2(L, b->C); break;
+    case PJ_BASIS_HAAR: make_haar(L, b->C); break;
+    case PJ_BASIS_IDENTITY:
+        for (int i = 0; i < L; ++i) b->C[(size_t)i * L + i] = 1.0;
+        break;
+    default: std::memcpy(b->C.data(), C, n * sizeof(double)); break;
+    }
+    if (kind == PJ_BASIS_CUSTOM) {
+        if (!invert_lu(L, b->C, b->D)) {
+            delete b;
+            return PJ_ERR_SINGULAR;
+        }
+    } else {   // orthonormal kinds: D = C^T
+        for (int t = 0; t < L; ++t)
+            for (int l = 0; l < L; ++l) b->D[(size_t)l * L + t] = b->C[(size_t)t * L + l];
+    }
+    upload(b);
+    *out = b;
+    return PJ_OK;
+}
+
+int pj_basis_get(pj_basis b, double* C_out, double* D_out)
+{
+    if (!b) return PJ_ERR_ARG;
+    const size_t n = (size_t)b->L * b->L;
+    if (C_out) std::memcpy(C_out, b->C.data(), n * sizeof(double));
+    if (D_out) std::memcpy(D_out, b->D.data(), n * sizeof(double));
+    return PJ_OK;
+}
+
+int pj_basis_L(pj_basis b) { return b ? b->L : PJ_ERR_ARG; }
+
+int pj_basis_destroy(pj_basis b)
+{
+    if (!b) return PJ_ERR_ARG;
+    free_device(b);
+    delete b;
+    return PJ_OK;
+}
+
+size_t pj_packed_bytes(int rows, int K, int L, int rmax, int prec)
+{
+    if (rows < 1 || K < 1 || L < 1 || L > kMaxL || rmax < 1 || rmax > L || !valid_prec(prec)) return 0;
+    return (size_t)pack_geom(rows, K, L, rmax, prec).total;
+}
+
+size_t pj_gemm_workspace_bytes(int M, int W, int K, int L, int r, int prec)
+{
+    size_t a = pj_packed_bytes(M, K, L, r, prec), b = pj_packed_bytes(W, K, L, r, prec);
+    if (!a || !b) return 0;
+    return align256(a) + align256(b);
+}
+
+int pj_pack_a(pj_basis b, int rmax, char transA, int M, int K, const void* A, int64_t lda, int prec,
+              void* packed, size_t packed_bytes, void* stream)
+{
+    int rc = check_pack(b, rmax, transA, M, K, A, lda, prec, packed, packed_bytes);
+    if (rc != PJ_OK) return rc;
+    return do_pack(b, rmax, true, transA, M, K, A, lda, prec, packed, stream);
+}
+
+int pj_pack_b(pj_basis b, int rmax, char transB, int W, int K, const void* B, int64_t ldb, int prec,
+              void* packed, size_t packed_bytes, void* stream)
+{
+    // B side: 'N' means B is K x W, so the required leading dimension is W
+    if (!b || !B || !packed) return PJ_ERR_ARG;
+    if (!is_n(transB) && !is_t(transB)) return PJ_ERR_ARG;
+    if (W >= 1 && K >= 1 && ldb < (is_n(transB) ? (int64_t)W : (int64_t)K)) return PJ_ERR_SHAPE;
+    int rc = check_pack(b, rmax, is_n(transB) ? 'T' : 'N', W, K, B, ldb, prec, packed, packed_bytes);
+    if (rc != PJ_OK) return rc;
+    return do_pack(b, rmax, false, transB, W, K, B, ldb, prec, packed, stream);
+}
+
+int pj_gemm_packed(int r, int M, int W, int K, int L, int prec, const void* Ap, int rmax_a, size_t a_bytes,
+                   const void* Bp, int rmax_b, size_t b_bytes, float beta, void* R, int64_t ldr, void* stream)
+{
+    if (!Ap || !Bp || !R) return PJ_ERR_ARG;
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    if (L < 1 || L > kMaxL) return PJ_ERR_ARG;
+    if (r < 1 || r > L || rmax_a < r || rmax_b < r || rmax_a > L || rmax_b > L) return PJ_ERR_ARG;
+    if (M < 1 || W < 1 || K < 1) return PJ_ERR_SHAPE;
+    if (ldr < W) return PJ_ERR_SHAPE;
+    if ((prec == PJ_FP8 || prec == PJ_FP8X2) && r > 8) return PJ_ERR_UNSUPPORTED;
+    if (!implemented_prec(prec)) return PJ_ERR_UNSUPPORTED;
+    if (a_bytes < (size_t)pack_geom(M, K, L, rmax_a, prec).total ||
+        b_bytes < (size_t)pack_geom(W, K, L, rmax_b, prec).total)
+        return PJ_ERR_WORKSPACE;
+    GemmArgs g;
+    g.X = Ap;
+    g.gx = pack_geom(M, K, L, rmax_a, prec);
+    g.Y = Bp;
+    g.gy = pack_geom(W, K, L, rmax_b, prec);
+    g.nkb = (int64_t)r * g.gx.Gp / layout_of(prec).KB;
+    g.P = M;
+    g.Q = W;
+    g.R = R;
+    g.ldr = ldr;
+    g.beta = beta;
+    int rc = launch_gemm(prec, g, (hipStream_t)stream);
+    return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
+}
+
+int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
+              const void* B, int64_t ldb, float beta, void* R, int64_t ldr, int prec, void* ws, size_t ws_bytes,
+              void* stream)
+{
+    if (!b || !A || !B || !R) return PJ_ERR_ARG;
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    if (r < 1 || r > b->L) return PJ_ERR_ARG;
+    if ((!is_n(transA) && !is_t(transA)) || (!is_n(transB) && !is_t(transB))) return PJ_ERR_ARG;
+    if (M < 1 || W < 1 || K < 1) return PJ_ERR_SHAPE;
+    if (lda < (is_n(transA) ? (int64_t)K : (int64_t)M)) return PJ_ERR_SHAPE;
+    if (ldb < (is_n(transB) ? (int64_t)W : (int64_t)K)) return PJ_ERR_SHAPE;
+    if (ldr < W) return PJ_ERR_SHAPE;
+    if ((prec == PJ_FP8 || prec == PJ_FP8X2) && r > 8) return PJ_ERR_UNSUPPORTED;
+    if (!implemented_prec(prec)) return PJ_ERR_UNSUPPORTED;
+    const size_t need = pj_gemm_workspace_bytes(M, W, K, b->L, r, prec);
+    if (!ws || ws_bytes < need) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    char* wa = (char*)ws;
+    char* wb = wa + align256(pj_packed_bytes(M, K, b->L, r, prec));
+    int rc = do_pack(b, r, true, transA, M, K, A, lda, prec, wa, stream);
+    if (rc != PJ_OK) return rc;
+    rc = do_pack(b, r, false, transB, W, K, B, ldb, prec, wb, stream);
+    if (rc != PJ_OK) return rc;
+    return pj_gemm_packed(r, M, W, K, b->L, prec, wa, r, pj_packed_bytes(M, K, b->L, r, prec), wb, r,
+                          pj_packed_bytes(W, K, b->L, r, prec), beta, R, ldr, stream);
+}
+
+size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec)
+{
+    if (W < 1 || N < 1 || N > W || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
+    return (size_t)conv_geom(W, N, L, r).total;
+}
+
+int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k, float* y,
+                int prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!b || !s || !k || !y) return PJ_ERR_ARG;
+    if (r < 1 || r > b->L) return PJ_ERR_ARG;
+    if (mode != PJ_XCORR && mode != PJ_CONV) return PJ_ERR_ARG;
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    if (W < 1 || N < 1 || N > W) return PJ_ERR_SHAPE;
+    if (prec != PJ_F32) return PJ_ERR_UNSUPPORTED;
+    const ConvGeom g = conv_geom(W, N, b->L, r);
+    if (g.tiles_m * 4 > 0x7fffffff || g.k_nrb * g.k_nkb * 64 / 256 > 0x7fffffff) return PJ_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < (size_t)g.total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    ConvArgs a;
+    a.s = s; a.W = W; a.k = k; a.N = N;
+    a.reverse = (mode == PJ_CONV);
+    a.L = b->L; a.r = r;
+    a.C = b->Cf; a.DT = b->DTf;
+    a.y = y; a.ws = ws;
+    return launch_conv(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
+}
+
+}  // extern "C"

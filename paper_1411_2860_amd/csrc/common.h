@@ -1,0 +1,148 @@
+// common.h -- internal definitions shared by the host code and the HIP
+// kernels of libprojgemm: packed-operand layouts, MFMA operand traits and
+// small helpers.  Not part of the public ABI (include/projgemm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pj {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_F16 = 4, P_F16X3 = 5, P_FP8 = 6, P_FP8X2 = 7 };
+
+// ---------------------------------------------------------------------------
+// Packed ("fragment-order") operand layout.
+//
+// A packed operand X has `rows` rows and a contraction length Kc.  It is cut
+// into tiles of RB rows x KB contraction indices.  A tile is exactly what one
+// 64-lane wavefront feeds to the matrix cores for that slice of the
+// contraction: lane i = g * RB + row holds the E consecutive indices
+// g*E .. g*E+E-1 of row `row` (g < NG = 64 / RB).  One tile is 64 * LB bytes
+// (LB = E * element bytes) and a wave loads it with one fully coalesced
+// LB-byte access per lane.
+//
+// Tiles are stored [plane][row_block][k_block][lane][LB], then, for FP8,
+// one E8M0 scale byte per lane per tile: [plane][row_block][k_block][lane].
+//
+// Projected operands use the contraction order k = l * Gp + j (projection
+// major, group j < G zero-padded up to Gp = roundup(G, KB)), so the first
+// r * Gp / KB k-blocks of a row block are exactly the first r projections:
+// one buffer packed at rmax serves every r <= rmax.
+// ---------------------------------------------------------------------------
+struct Layout {
+    int elem;    // bytes per element
+    int RB;      // rows per tile
+    int NG;      // lane groups along the contraction (64 / RB)
+    int E;       // consecutive contraction indices per lane
+    int KB;      // contraction indices per tile (NG * E)
+    int LB;      // bytes per lane per tile
+    int planes;  // 1, or 2 for hi + lo split modes
+    int scales;  // 1 if an E8M0 scale byte accompanies each lane vector
+};
+
+__host__ __device__ constexpr Layout layout_of(int prec)
+{
+    switch (prec) {
+    case P_F64:   return Layout{8, 16, 4, 2, 8, 16, 1, 0};
+    case P_F32:   return Layout{4, 32, 2, 4, 8, 16, 1, 0};
+    case P_BF16:  return Layout{2, 32, 2, 8, 16, 16, 1, 0};
+    case P_BF16X3:return Layout{2, 32, 2, 8, 16, 16, 2, 0};
+    case P_F16:   return Layout{2, 32, 2, 8, 16, 16, 1, 0};
+    case P_F16X3: return Layout{2, 32, 2, 8, 16, 16, 2, 0};
+    case P_FP8:   return Layout{1, 32, 2, 32, 64, 32, 1, 1};
+    case P_FP8X2: return Layout{1, 32, 2, 32, 64, 32, 2, 1};
+    default:      return Layout{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+}
+
+__host__ __device__ constexpr int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ constexpr int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+// Geometry of one packed operand.
+struct PackGeom {
+    int64_t rows, K;
+    int L, rmax;
+    int64_t G, Gp;       // groups, padded groups
+    int64_t nrb, nkb;    // row blocks, k-blocks per row block
+    int64_t plane_bytes; // bytes of one plane of tiles
+    int64_t scale_plane; // bytes of one plane of scales
+    int64_t total;       // all bytes
+};
+
+inline PackGeom pack_geom(int64_t rows, int64_t K, int L, int rmax, int prec)
+{
+    Layout ly = layout_of(prec);
+    PackGeom g;
+    g.rows = rows; g.K = K; g.L = L; g.rmax = rmax;
+    g.G = cdiv(K, L);
+    g.Gp = rup(g.G, ly.KB);
+    g.nrb = cdiv(rows, ly.RB);
+    g.nkb = (int64_t)rmax * g.Gp / ly.KB;
+    g.plane_bytes = g.nrb * g.nkb * 64 * ly.LB;
+    g.scale_plane = ly.scales ? g.nrb * g.nkb * 64 : 0;
+    g.total = ly.planes * (g.plane_bytes + g.scale_plane);
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Vector types for MFMA operands.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// Launch helpers implemented in the .hip files (host side).
+struct PackArgs {
+    const void* X;     // float or double source
+    int64_t ld;        // leading dimension of X in elements
+    int trans;         // 0: element (p, k) at X[p*ld + k]; 1: at X[k*ld + p]
+    int64_t P, K;      // rows and contraction length of the source
+    int L, r;          // projection size, projections to pack (r <= rmax)
+    const void* coef;  // L x L row-major, element (t, l) = coefficient of
+                       // source index t in projection l (float or double)
+    void* out;         // packed operand
+    PackGeom geom;
+};
+int launch_pack(int prec, const PackArgs& a, hipStream_t s);
+
+struct GemmArgs {
+    const void* X; PackGeom gx;  // P rows
+    const void* Y; PackGeom gy;  // Q rows
+    int64_t nkb;                 // k-blocks to contract (r * Gp / KB)
+    int64_t P, Q;
+    void* R; int64_t ldr;        // P x Q row-major, float (double for F64)
+    float beta;
+};
+int launch_gemm(int prec, const GemmArgs& a, hipStream_t s);
+
+// Projected cross-correlation (conv.hip).
+struct ConvGeom {
+    int64_t nout;      // W - N + 1 valid outputs
+    int64_t nc, ncp;   // kernel phases per projection (N + L - 2) / L + 1, padded to 8
+    int64_t rows;      // output rows a (outputs m = a L + b)
+    int64_t tiles_m;   // row tiles of the reduced cross-correlation
+    int64_t nbp;       // length of each projected-signal row
+    int64_t k_nrb, k_nkb;
+    int64_t sc_bytes, k_bytes, total;
+};
+ConvGeom conv_geom(int64_t W, int64_t N, int L, int r);
+
+struct ConvArgs {
+    const float* s; int64_t W;
+    const float* k; int64_t N;
+    int reverse;          // 1: convolution (kernel reversed), 0: cross-correlation
+    int L, r;
+    const float* C;       // C[t][l]
+    const float* DT;      // D^T[u][l] = D[l][u]
+    float* y;
+    void* ws;
+};
+int launch_conv(const ConvArgs& a, hipStream_t s);
+
+}  // namespace pj

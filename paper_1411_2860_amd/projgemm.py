@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libprojgemm.so (include/projgemm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI.  PyTorch supplies device memory (tensors, the
+workspace) and the current stream.  If the library is not built, every call
+raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+__all__ = [
+    "ProjGemmError", "lib", "lib_path", "Basis", "PREC", "BASIS",
+    "gemm", "pack_a", "pack_b", "gemm_packed", "packed_bytes", "gemm_workspace_bytes",
+    "conv1d", "conv1d_workspace_bytes",
+    "status_str",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libprojgemm.so")
+_lock = threading.Lock()
+_lib = None
+
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3, "f16": 4, "f16x3": 5, "fp8": 6, "fp8x2": 7}
+BASIS = {"dct2": 0, "haar": 1, "identity": 2, "custom": 3}
+STATUS = {0: "PJ_OK", -1: "PJ_ERR_ARG", -2: "PJ_ERR_SHAPE", -3: "PJ_ERR_UNSUPPORTED",
+          -4: "PJ_ERR_WORKSPACE", -5: "PJ_ERR_SINGULAR", -6: "PJ_ERR_HIP"}
+
+
+class ProjGemmError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({status_str(code)})")
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+_ch = ctypes.c_char
+_f = ctypes.c_float
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGNATURES = {
+    "pj_status_str": (ctypes.c_char_p, [_i]),
+    "pj_basis_create": (_i, [ctypes.POINTER(_vp), _i, _i, _dp]),
+    "pj_basis_get": (_i, [_vp, _dp, _dp]),
+    "pj_basis_L": (_i, [_vp]),
+    "pj_basis_destroy": (_i, [_vp]),
+    "pj_gemm_workspace_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
+    "pj_packed_bytes": (_sz, [_i, _i, _i, _i, _i]),
+    "proj_gemm": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _f, _vp, _i64, _i, _vp, _sz, _vp]),
+    "pj_pack_a": (_i, [_vp, _i, _ch, _i, _i, _vp, _i64, _i, _vp, _sz, _vp]),
+    "pj_pack_b": (_i, [_vp, _i, _ch, _i, _i, _vp, _i64, _i, _vp, _sz, _vp]),
+    "pj_gemm_packed": (_i, [_i, _i, _i, _i, _i, _i, _vp, _i, _sz, _vp, _i, _sz, _f, _vp, _i64, _vp]),
+    "pj_conv1d_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i]),
+    "proj_conv1d": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
+}
+
+
+def lib():
+    """The loaded library; raises if libprojgemm.so has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                                   "`python -m paper_1411_2860_amd.build` (no fallback exists)")
+            L = ctypes.CDLL(_LIB_PATH)
+            for name, (res, args) in _SIGNATURES.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def status_str(code: int) -> str:
+    try:
+        return lib().pj_status_str(code).decode()
+    except Exception:  # the library itself may be what is missing
+        return "?"
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise ProjGemmError(code, what)
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class Basis:
+    """An L x L projection basis C with D = C^{-1} (eq. (5)-(7)), built in FP64
+    by the library and uploaded to the current device."""
+
+    def __init__(self, kind: str = "dct2", L: int = 8, C=None):
+        self._h = _vp()
+        arr = None
+        if C is not None:
+            arr = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+            if arr.shape != (L, L):
+                raise ValueError("custom basis must be L x L")
+        cp = arr.ctypes.data_as(_dp) if arr is not None else None
+        _check(lib().pj_basis_create(ctypes.byref(self._h), BASIS[kind], L, cp), "pj_basis_create")
+        self.kind, self.L = kind, L
+
+    @property
+    def handle(self):
+        return self._h
+
+    def matrices(self):
+        """FP64 (C, D) as stored by the library."""
+        C = np.empty((self.L, self.L))
+        D = np.empty((self.L, self.L))
+        _check(lib().pj_basis_get(self._h, C.ctypes.data_as(_dp), D.ctypes.data_as(_dp)), "pj_basis_get")
+        return C, D
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().pj_basis_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def packed_bytes(rows: int, K: int, L: int, rmax: int, prec="f32") -> int:
+    return int(lib().pj_packed_bytes(rows, K, L, rmax, _prec(prec)))
+
+
+def gemm_workspace_bytes(M: int, W: int, K: int, L: int, r: int, prec="f32") -> int:
+    return int(lib().pj_gemm_workspace_bytes(M, W, K, L, r, _prec(prec)))
+
+
+def _byte_buffer(nbytes: int, device):
+    import torch
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def gemm(A, B, r: int, basis: Basis, prec="f32", transA=False, transB=False, beta=0.0, out=None,
+         workspace=None, stream=None):
+    """R = A Q_{r,K} B (+ beta R).  A is M x K (K x M if transA), B is K x W
+    (W x K if transB); row-major CUDA tensors of float32 (float64 for 'f64')."""
+    import torch
+    p = _prec(prec)
+    if transA:
+        K, M = A.shape
+    else:
+        M, K = A.shape
+    if transB:
+        W, K2 = B.shape
+    else:
+        K2, W = B.shape
+    if K2 != K:
+        raise ValueError(f"contraction mismatch {K} vs {K2}")
+    dt = torch.float64 if p == PREC["f64"] else torch.float32
+    if A.dtype != dt or B.dtype != dt:
+        raise TypeError(f"A and B must be {dt}")
+    if A.stride(1) != 1 or B.stride(1) != 1:
+        raise ValueError("A and B need unit stride along their last dimension")
+    if out is None:
+        out = torch.empty((M, W), dtype=dt, device=A.device)
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs `out`")
+    need = gemm_workspace_bytes(M, W, K, basis.L, r, p)
+    if workspace is None:
+        workspace = _byte_buffer(need, A.device)
+    _check(lib().proj_gemm(basis.handle, r, b"T" if transA else b"N", b"T" if transB else b"N", M, W, K,
+                           _ptr(A), A.stride(0), _ptr(B), B.stride(0), float(beta), _ptr(out), out.stride(0), p,
+                           _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)),
+           "proj_gemm")
+    return out
+
+
+def pack_a(A, rmax: int, basis: Basis, prec="f32", transA=False, out=None, stream=None):
+    """Projects and packs the A side at rmax projections; returns a byte tensor."""
+    p = _prec(prec)
+    if transA:
+        K, M = A.shape
+    else:
+        M, K = A.shape
+    n = packed_bytes(M, K, basis.L, rmax, p)
+    if out is None:
+        out = _byte_buffer(n, A.device)
+    _check(lib().pj_pack_a(basis.handle, rmax, b"T" if transA else b"N", M, K, _ptr(A), A.stride(0), p,
+                           _ptr(out), out.numel(), _stream(stream)), "pj_pack_a")
+    return out
+
+
+def pack_b(B, rmax: int, basis: Basis, prec="f32", transB=False, out=None, stream=None):
+    """Projects and packs the B side at rmax projections; returns a byte tensor."""
+    p = _prec(prec)
+    if transB:
+        W, K = B.shape
+    else:
+        K, W = B.shape
+    n = packed_bytes(W, K, basis.L, rmax, p)
+    if out is None:
+        out = _byte_buffer(n, B.device)
+    _check(lib().pj_pack_b(basis.handle, rmax, b"T" if transB else b"N", W, K, _ptr(B), B.stride(0), p,
+                           _ptr(out), out.numel(), _stream(stream)), "pj_pack_b")
+    return out
+
+
+def gemm_packed(Ap, Bp, r: int, M: int, W: int, K: int, L: int, rmax_a: int, rmax_b: int, prec="f32",
+                beta=0.0, out=None, stream=None):
+    """R = sum_{l<r} A_c^{(l)} B_d^{(l)} (+ beta R) from packed operands."""
+    import torch
+    p = _prec(prec)
+    dt = torch.float64 if p == PREC["f64"] else torch.float32
+    if out is None:
+        out = torch.empty((M, W), dtype=dt, device=Ap.device)
+    _check(lib().pj_gemm_packed(r, M, W, K, L, p, _ptr(Ap), rmax_a, Ap.numel(), _ptr(Bp), rmax_b, Bp.numel(),
+                                float(beta), _ptr(out), out.stride(0), _stream(stream)), "pj_gemm_packed")
+    return out
+
+
+def conv1d_workspace_bytes(W: int, N: int, L: int, r: int, prec="f32") -> int:
+    return int(lib().pj_conv1d_workspace_bytes(W, N, L, r, _prec(prec)))
+
+
+def conv1d(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, workspace=None, stream=None):
+    """Projected valid cross-correlation (mode 'xcorr') or convolution
+    ('conv') of the 1-D float32 CUDA tensors s (W) and k (N): W - N + 1 outputs."""
+    import torch
+    Wn, N = s.numel(), k.numel()
+    if s.dtype != torch.float32 or k.dtype != torch.float32:
+        raise TypeError("s and k must be float32")
+    if not (s.is_contiguous() and k.is_contiguous()):
+        raise ValueError("s and k must be contiguous")
+    if out is None:
+        out = torch.empty(max(Wn - N + 1, 1), dtype=torch.float32, device=s.device)
+    need = conv1d_workspace_bytes(Wn, N, basis.L, r, prec)
+    if workspace is None:
+        workspace = _byte_buffer(need, s.device)
+    _check(lib().proj_conv1d(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], Wn, _ptr(s), N, _ptr(k), _ptr(out),
+                             _prec(prec), _ptr(workspace), workspace.numel(), _stream(stream)), "proj_conv1d")
+    return out

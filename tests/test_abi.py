@@ -1,0 +1,160 @@
+"""CPU tests of the C ABI: the library loads, exports every function that
+include/projgemm.h declares, rejects invalid calls with the documented status
+before touching a device, and builds its FP64 bases correctly on the host.
+No compute call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_2860_amd import projgemm as pg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "projgemm.h")
+
+OK, ARG, SHAPE, UNSUP, WS, SING, HIP = 0, -1, -2, -3, -4, -5, -6
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(p[jr]\w*)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pg.lib_path()):
+        pytest.fail("libprojgemm.so is not built (python -m paper_1411_2860_amd.build)")
+    return pg.lib()
+
+
+@pytest.fixture(scope="module")
+def basis16(lib):
+    return pg.Basis("dct2", 16)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    raw = ctypes.CDLL(pg.lib_path())
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+    for n in names:
+        assert n in pg._SIGNATURES, f"binding lacks {n}"
+
+
+def test_status_strings(lib):
+    for c in (OK, ARG, SHAPE, UNSUP, WS, SING, HIP):
+        assert pg.status_str(c) and pg.status_str(c) != "unknown status"
+
+
+# ------------------------------------------------------------------ basis
+
+@pytest.mark.parametrize("kind,L", [("dct2", 1), ("dct2", 16), ("dct2", 64), ("dct2", 256), ("haar", 2),
+                                    ("haar", 8), ("haar", 256), ("identity", 5)])
+def test_basis_inverse_orthonormal_and_same_projector_as_oracle(kind, L):
+    b = pg.Basis(kind, L)
+    C, D = b.matrices()
+    np.testing.assert_allclose(D @ C, np.eye(L), atol=1e-12)
+    np.testing.assert_allclose(C.T @ C, np.eye(L), atol=1e-12)
+    Co, Do = oracle.basis(kind, L)
+    for r in sorted({1, 2, max(1, L // 2), L}):
+        # column scaling does not change Q_r, and both orderings agree
+        np.testing.assert_allclose(C[:, :r] @ D[:r, :], Co[:, :r] @ Do[:r, :], atol=1e-12)
+    assert pg.lib().pj_basis_L(b.handle) == L
+
+
+def test_custom_basis_and_singular(lib):
+    C = np.random.default_rng(0).standard_normal((6, 6)) + 3 * np.eye(6)
+    b = pg.Basis("custom", 6, C)
+    Cb, Db = b.matrices()
+    np.testing.assert_array_equal(Cb, C)
+    np.testing.assert_allclose(Db @ C, np.eye(6), atol=1e-12)
+    S = C.copy()
+    S[:, 2] = S[:, 0]
+    h = ctypes.c_void_p()
+    arr = np.ascontiguousarray(S)
+    assert lib.pj_basis_create(ctypes.byref(h), 3, 6, arr.ctypes.data_as(pg._dp)) == SING
+
+
+def test_basis_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert lib.pj_basis_create(None, 0, 8, None) == ARG
+    assert lib.pj_basis_create(ctypes.byref(h), 0, 0, None) == ARG
+    assert lib.pj_basis_create(ctypes.byref(h), 0, 257, None) == ARG
+    assert lib.pj_basis_create(ctypes.byref(h), 1, 6, None) == ARG        # Haar needs a power of two
+    assert lib.pj_basis_create(ctypes.byref(h), 3, 4, None) == ARG        # custom needs C
+    assert lib.pj_basis_create(ctypes.byref(h), 9, 4, None) == ARG
+    assert lib.pj_basis_get(None, None, None) == ARG
+    assert lib.pj_basis_destroy(None) == ARG
+
+
+# ------------------------------------------------------------ sizes
+
+def test_packed_bytes_and_workspace(lib):
+    # f32: tiles of 32 rows x 8 indices, 1 KiB each; K = 4096, L = 64 -> G = 64
+    assert pg.packed_bytes(1024, 4096, 64, 16, "f32") == (1024 // 32) * (16 * 64 // 8) * 1024
+    # ragged: rows padded to 32, groups padded to a multiple of 8
+    assert pg.packed_bytes(33, 100, 16, 3, "f32") == 2 * (3 * 8 // 8) * 1024
+    # split modes store two planes
+    assert pg.packed_bytes(64, 256, 16, 4, "bf16x3") == 2 * pg.packed_bytes(64, 256, 16, 4, "bf16")
+    assert pg.packed_bytes(0, 10, 4, 1) == 0 and pg.packed_bytes(4, 10, 4, 5) == 0
+    ws = pg.gemm_workspace_bytes(100, 200, 300, 16, 4, "f32")
+    assert ws >= pg.packed_bytes(100, 300, 16, 4) + pg.packed_bytes(200, 300, 16, 4)
+    assert pg.gemm_workspace_bytes(100, 200, 300, 16, 17, "f32") == 0
+
+
+# ------------------------------------------------------- proj_gemm errors
+
+def _gemm(lib, b, r=4, ta=b"N", tb=b"N", M=8, W=8, K=32, lda=32, ldb=8, ldr=8, prec=1, ws_bytes=1 << 30,
+          A=FAKE, B=FAKE, R=FAKE, ws=FAKE):
+    return lib.proj_gemm(b.handle if b is not None else None, r, ta, tb, M, W, K, A, lda, B, ldb, 0.0, R, ldr,
+                         prec, ws, ws_bytes, None)
+
+
+def test_proj_gemm_validation(lib, basis16):
+    b = basis16
+    assert _gemm(lib, None) == ARG
+    assert _gemm(lib, b, A=None) == ARG
+    assert _gemm(lib, b, R=None) == ARG
+    assert _gemm(lib, b, r=0) == ARG
+    assert _gemm(lib, b, r=17) == ARG
+    assert _gemm(lib, b, ta=b"X") == ARG
+    assert _gemm(lib, b, prec=8) == ARG
+    assert _gemm(lib, b, M=0) == SHAPE
+    assert _gemm(lib, b, K=-1) == SHAPE
+    assert _gemm(lib, b, lda=31) == SHAPE
+    assert _gemm(lib, b, ta=b"T", lda=7) == SHAPE          # A stored K x M needs lda >= M
+    assert _gemm(lib, b, ldb=7) == SHAPE
+    assert _gemm(lib, b, tb=b"T", ldb=31) == SHAPE         # B stored W x K needs ldb >= K
+    assert _gemm(lib, b, ldr=7) == SHAPE
+    assert _gemm(lib, b, prec=6, r=9) == UNSUP             # FP8 only for r <= 8
+    assert _gemm(lib, b, ws_bytes=16) == WS
+    assert _gemm(lib, b, ws=None) == WS
+
+
+def test_valid_call_without_device_reports_hip(lib, basis16):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    assert _gemm(lib, basis16) == HIP
+
+
+def test_pack_and_packed_gemm_validation(lib, basis16):
+    b = basis16
+    n = pg.packed_bytes(8, 32, 16, 4)
+    assert lib.pj_pack_a(b.handle, 0, b"N", 8, 32, FAKE, 32, 1, FAKE, n, None) == ARG
+    assert lib.pj_pack_a(b.handle, 4, b"N", 8, 32, FAKE, 31, 1, FAKE, n, None) == SHAPE
+    assert lib.pj_pack_a(b.handle, 4, b"N", 8, 32, FAKE, 32, 1, FAKE, n - 1, None) == WS
+    assert lib.pj_pack_b(b.handle, 4, b"N", 8, 32, FAKE, 7, 1, FAKE, n, None) == SHAPE
+    assert lib.pj_pack_b(b.handle, 4, b"T", 8, 32, FAKE, 31, 1, FAKE, n, None) == SHAPE
+    assert lib.pj_pack_b(b.handle, 4, b"Q", 8, 32, FAKE, 32, 1, FAKE, n, None) == ARG
+    assert lib.pj_gemm_packed(5, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 8, n, 0.0, FAKE, 8, None) == ARG
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 4, n, 0.0, FAKE, 7, None) == SHAPE
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, None, 4, n, FAKE, 4, n, 0.0, FAKE, 8, None) == ARG
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n - 1, FAKE, 4, n, 0.0, FAKE, 8, None) == WS
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 8, n, 0.0, FAKE, 8, None) == WS

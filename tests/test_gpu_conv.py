@@ -1,0 +1,123 @@
+"""GPU parity of the projected 1-D cross-correlation / convolution against the
+FP64 oracle, element by element within a derived rounding bound.
+
+Paper: Sec. II-B eq. (3); Sec. III-A eq. (10)-(14); Sec. III-B (projection
+during the blocking of the signal and of the kernel)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_2860_amd import inputs
+from tests import _tol
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1411_2860_amd import projgemm
+    projgemm.lib()
+    return projgemm
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def conv_bound(L, r, N, mag, safety=4.0):
+    """Each output sums r * ncp products of two L-term FP32 dot products,
+    accumulated in FP32 (see tests/_tol.py for the derivation)."""
+    u = _tol.U["f32"]
+    ncp = -(-((N + L - 2) // L + 1) // 8) * 8
+    g = lambda m: m * u / (1 - m * u)
+    return safety * (2 * g(L) + g(r * ncp) + u) * mag
+
+
+def _check(pg, s, k, kind, L, r, mode="xcorr"):
+    basis = pg.Basis(kind, L)
+    C, D = basis.matrices()
+    y = pg.conv1d(_dev(s), _dev(k), r, basis, mode=mode)
+    torch.cuda.synchronize()
+    got = y.double().cpu().numpy()
+    kk = k[::-1] if mode == "conv" else k
+    ref = oracle.xcorr_proj(s, kk, C, D, r)
+    mag = oracle.xcorr_proj(np.abs(s), np.abs(kk), np.abs(C), np.abs(D), r)
+    _tol.assert_within(got, ref, conv_bound(L, r, k.size, mag), f"{kind} L={L} r={r} N={k.size} {mode}")
+    return got, ref
+
+
+@pytest.mark.parametrize("r", [1, 2, 5, 16])
+def test_small_dct16(pg, r):
+    s = inputs.ar2_signal(3000, seed=21, burn=512)
+    k, _ = inputs.excerpt_kernel(s, 100, seed=22)
+    got, ref = _check(pg, s, k, "dct2", 16, r)
+    if r == 16:
+        assert oracle.rel_fro(got, np.correlate(s, k, "valid")) < 1e-5
+
+
+@pytest.mark.parametrize("L", [2, 4])
+@pytest.mark.parametrize("N", [600, 1200])
+def test_paper_operating_points_haar(pg, L, N):
+    """Block of 20000 samples, kernels of 600 / 1200 samples, L = 2 and 4 Haar
+    (the CONV and music-matching settings of Sec. IV-A and V-B), one
+    projection and all projections."""
+    s = inputs.ar2_signal(20000, seed=23)
+    k, _ = inputs.excerpt_kernel(s, N, seed=24)
+    for r in (1, L):
+        _check(pg, s, k, "haar", L, r)
+
+
+@pytest.mark.parametrize("W,N,L,kind", [
+    (1000, 1, 8, "dct2"),       # N = 1
+    (257, 257, 16, "dct2"),     # N = W: one output
+    (999, 37, 16, "haar"),      # nothing aligned
+    (513, 64, 1, "identity"),   # L = 1: plain cross-correlation
+    (4099, 300, 256, "dct2"),   # largest L
+    (700, 33, 5, "dct2"),       # L not a power of two
+])
+def test_ragged(pg, W, N, L, kind):
+    rng = np.random.default_rng(W + N)
+    s, k = rng.standard_normal(W), rng.standard_normal(N)
+    for r in sorted({1, max(1, L // 2), L}):
+        _check(pg, s, k, kind, L, r)
+
+
+@pytest.mark.parametrize("r", [1, 3, 8])
+def test_convolution_mode(pg, r):
+    s = inputs.ar2_signal(5000, seed=25)
+    k, _ = inputs.excerpt_kernel(s, 200, seed=26)
+    got, _ = _check(pg, s, k, "dct2", 8, r, mode="conv")
+    if r == 8:
+        assert oracle.rel_fro(got, np.convolve(s, k, "valid")) < 1e-5
+
+
+@pytest.fixture(scope="module")
+def long_signal():
+    return inputs.ar2_signal(1 << 22, seed=inputs.SEED_AR2)
+
+
+@pytest.mark.parametrize("N", [1024, 4096, 16384])
+@pytest.mark.parametrize("r", [1, 16, 256])
+def test_full_size_sampled(pg, long_signal, N, r):
+    """2^22-sample AR(2) signal, kernel excerpts of 1024 / 4096 / 16384
+    samples, L = 256 DCT-II; 512 sampled outputs (including both ends)
+    against the oracle; exact at r = L."""
+    s = long_signal
+    k, o = inputs.excerpt_kernel(s, N, seed=inputs.SEED_KERNEL)
+    basis = pg.Basis("dct2", 256)
+    C, D = basis.matrices()
+    y = pg.conv1d(_dev(s), _dev(k), r, basis)
+    torch.cuda.synchronize()
+    nout = s.size - N + 1
+    rng = np.random.default_rng(N + r)
+    ms = np.unique(np.concatenate([[0, 1, 255, 256, nout - 1, o], rng.integers(0, nout, 506)]))
+    got = y[torch.from_numpy(ms).cuda()].double().cpu().numpy()
+    ref = oracle.xcorr_proj_at(s, k, C, D, r, ms)
+    mag = oracle.xcorr_proj_at(np.abs(s), np.abs(k), np.abs(C), np.abs(D), r, ms)
+    _tol.assert_within(got, ref, conv_bound(256, r, N, mag), f"full size N={N} r={r}")
+    if r == 256:
+        exact = np.array([np.dot(k, s[m:m + N]) for m in ms])
+        assert oracle.rel_fro(got, exact) < 1e-5

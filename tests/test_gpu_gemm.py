@@ -1,0 +1,179 @@
+"""GPU parity of the projected GEMM (C ABI through the ctypes binding) against
+the FP64 oracle, element by element within the derived rounding bound
+(tests/_tol.py), on the seeded synthetic inputs.
+
+Paper: Sec. III-A/B, eq. (5)-(8), (15)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_2860_amd import inputs
+from tests import _tol
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+KB = {"f64": 8, "f32": 8, "bf16": 16, "f16": 16, "bf16x3": 16, "f16x3": 16}
+
+
+@pytest.fixture(scope="module")
+def pg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1411_2860_amd import projgemm
+    projgemm.lib()
+    return projgemm
+
+
+def _dev(x, dt):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dt)
+
+
+def _run(pg, A, B, basis, r, prec, transA=False, transB=False):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Ad = _dev(A.T if transA else A, dt)
+    Bd = _dev(B.T if transB else B, dt)
+    R = pg.gemm(Ad, Bd, r, basis, prec=prec, transA=transA, transB=transB)
+    torch.cuda.synchronize()
+    return R.double().cpu().numpy()
+
+
+def _check(pg, A, B, kind, L, r, prec, transA=False, transB=False, Cc=None):
+    basis = pg.Basis(kind, L, Cc)
+    C, D = basis.matrices()          # the library's own FP64 basis (any column scaling)
+    got = _run(pg, A, B, basis, r, prec, transA, transB)
+    ref = oracle.gemm_proj(A, B, C, D, r)
+    if prec in ("f32", "f64"):
+        # the oracle's own basis gives the same projected product
+        Co, Do = (Cc, oracle.invert(Cc)) if kind == "custom" else oracle.basis(kind, L)
+        np.testing.assert_allclose(oracle.gemm_proj(A, B, Co, Do, r), ref, rtol=1e-9,
+                                   atol=1e-9 * np.abs(ref).max())
+    Gp = -(-(-(-A.shape[1] // L)) // KB[prec]) * KB[prec]
+    bound = _tol.gemm_bound(prec, L, r, Gp, _tol.magnitude(A, B, C, D, r))
+    _tol.assert_within(got, ref, bound, f"{kind} L={L} r={r} {prec}")
+    return got, ref
+
+
+# ------------------------------------------- FP64 parity configuration
+@pytest.mark.parametrize("r", [1, 2, 4, 8, 16])
+def test_fp64_parity_256_dct16(pg, r):
+    """M = K = W = 256, L = 16 DCT-II, A a smoothed 0..255 field (sigma 4),
+    B ~ N(0, 1); every r."""
+    A = inputs.smoothed_field(256, 256, sigma=4.0, seed=inputs.SEED_CFG1_A)
+    B = inputs.gaussian_matrix(256, 256, seed=inputs.SEED_CFG1_B)
+    got, ref = _check(pg, A, B, "dct2", 16, r, "f64")
+    if r == 16:
+        assert oracle.rel_fro(got, A @ B) < 1e-13
+
+
+# ----------------------------------- recognition-shaped GEMM, reduced size
+@pytest.fixture(scope="module")
+def images():
+    A = inputs.image_rows(96, seed_base=inputs.SEED_IMG_BASE)                 # queries
+    Bt = inputs.image_rows(160, seed_base=inputs.SEED_IMG_BASE, first=1024)   # database rows
+    return A, Bt
+
+
+@pytest.mark.parametrize("r", [1, 3, 8, 16, 64])
+def test_fp32_images_transB(pg, images, r):
+    """Queries x database^T with 64x64 images (K = 4096), L = 64 DCT-II."""
+    A, Bt = images
+    got, ref = _check(pg, A, Bt.T, "dct2", 64, r, "f32", transB=True)
+    if r == 64:
+        assert oracle.rel_fro(got, A @ Bt.T) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3", "f16", "f16x3"])
+@pytest.mark.parametrize("r", [1, 16, 64])
+def test_reduced_precision_images(pg, images, prec, r):
+    A, Bt = images
+    _check(pg, A, Bt.T, "dct2", 64, r, prec, transB=True)
+
+
+# ------------------------------------------------------ ragged and layouts
+@pytest.mark.parametrize("M,K,W,L,kind", [
+    (77, 1000, 45, 64, "dct2"),     # K not a multiple of L, ragged M and W
+    (33, 65, 31, 16, "haar"),
+    (1, 1, 1, 8, "dct2"),           # K < L
+    (130, 257, 70, 8, "identity"),
+    (64, 96, 96, 3, "custom"),      # L not a power of two
+    (300, 512, 129, 256, "dct2"),   # the largest L
+])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_ragged_shapes_all_r_edges(pg, M, K, W, L, kind, prec):
+    rng = np.random.default_rng(M * 7 + K)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, W))
+    Cc = rng.standard_normal((L, L)) + 2 * np.eye(L) if kind == "custom" else None
+    for r in sorted({1, max(1, L // 2), L}):
+        _check(pg, A, B, kind, L, r, prec, Cc=Cc)
+
+
+@pytest.mark.parametrize("transA,transB", [(False, False), (True, False), (False, True), (True, True)])
+def test_layouts(pg, transA, transB):
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((70, 200))
+    B = rng.standard_normal((200, 90))
+    _check(pg, A, B, "dct2", 16, 5, "f32", transA=transA, transB=transB)
+
+
+def test_beta_accumulates(pg):
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((40, 64)).astype(np.float32)
+    B = rng.standard_normal((64, 50)).astype(np.float32)
+    R0 = rng.standard_normal((40, 50)).astype(np.float32)
+    basis = pg.Basis("dct2", 16)
+    C, D = basis.matrices()
+    out = _dev(R0, torch.float32)
+    pg.gemm(_dev(A, torch.float32), _dev(B, torch.float32), 4, basis, beta=0.5, out=out)
+    torch.cuda.synchronize()
+    ref = 0.5 * R0 + oracle.gemm_proj(A, B, C, D, 4)
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=1e-5, atol=1e-4)
+
+
+def test_packed_once_serves_every_r(pg, images):
+    """A buffer packed at rmax gives, at every r <= rmax, exactly the result of
+    a pack at r (same kernels, same summation order)."""
+    A, Bt = images
+    basis = pg.Basis("dct2", 64)
+    Ad, Bd = _dev(A, torch.float32), _dev(Bt, torch.float32)
+    M, K = A.shape
+    W = Bt.shape[0]
+    Ap = pg.pack_a(Ad, 32, basis)
+    Bp = pg.pack_b(Bd, 32, basis, transB=True)
+    for r in (1, 7, 32):
+        a = pg.gemm_packed(Ap, Bp, r, M, W, K, 64, 32, 32)
+        b = pg.gemm(Ad, Bd, r, basis, transB=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+# ----------------------------------------- full recognition size, sampled
+@pytest.fixture(scope="module")
+def full_images():
+    A = inputs.image_rows(1024, seed_base=inputs.SEED_IMG_BASE)
+    Bt = inputs.image_rows(8192, seed_base=inputs.SEED_IMG_BASE, first=1024)
+    return A, Bt
+
+
+@pytest.mark.parametrize("r", [1, 16, 64])
+def test_full_size_sampled(pg, full_images, r):
+    """1024 queries x 8192 database images of 64 x 64, L = 64, FP32, in the
+    launch configuration the benchmark times; 48 x 48 sampled outputs
+    against the oracle; at r = L the sampled error against the exact product
+    is below 1e-5."""
+    A, Bt = full_images
+    basis = pg.Basis("dct2", 64)
+    C, D = basis.matrices()
+    R = pg.gemm(_dev(A, torch.float32), _dev(Bt, torch.float32), r, basis, transB=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(r)
+    rows = np.sort(rng.choice(1024, 48, replace=False))
+    cols = np.sort(rng.choice(8192, 48, replace=False))
+    got = R[torch.from_numpy(rows).cuda()][:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
+    ref = oracle.gemm_proj_block(A, Bt.T, C, D, r, rows, cols)
+    mag = oracle.gemm_proj_block(np.abs(A), np.abs(Bt.T), np.abs(C), np.abs(D), r, rows, cols)
+    _tol.assert_within(got, ref, _tol.gemm_bound("f32", 64, r, 64, mag), f"full size r={r}")
+    if r == 64:
+        exact = A[rows] @ Bt[cols].T
+        assert oracle.rel_fro(got, exact) < 1e-5
