@@ -57,10 +57,13 @@ def cpu_baseline(A, Bt, r):
     C, D = oracle.basis("dct2", L)
     cols = np.arange(W)
     Bk = np.ascontiguousarray(Bt.T)
-    t0 = time.perf_counter()
-    oracle.gemm_proj_block(A, Bk, C, D, r, np.arange(8), cols)
-    t_cal = time.perf_counter() - t0
-    rows = int(max(8, min(M, 8 * round(15.0 / max(t_cal, 1e-3)))))
+    def run(n):
+        t0 = time.perf_counter()
+        oracle.gemm_proj_block(A, Bk, C, D, r, np.arange(n), cols)
+        return time.perf_counter() - t0
+    t8, t40 = run(8), run(40)
+    per_row = max((t40 - t8) / 32.0, 1e-4)
+    rows = int((15.0 - t8) / per_row) if t8 < 15.0 else 8
     rows = min(M, max(8, rows // 8 * 8))
     t0 = time.perf_counter()
     oracle.gemm_proj_block(A, Bk, C, D, r, np.arange(rows), cols)
@@ -194,16 +197,18 @@ def main():
                           "method_rel_err": float(f"{e_method:.3e}")})
             del bufs_r
         out["per_r"] = per_r
-        # plain (unprojected) FP32 GEMM through the same kernels: identity basis, L = 1
-        plain = pg.Basis("identity", 1)
-        Ap = torch.empty(pg.packed_bytes(M, K, 1, 1), dtype=torch.uint8, device=dev)
-        Bp = torch.empty(pg.packed_bytes(W, K, 1, 1), dtype=torch.uint8, device=dev)
+        # plain (unprojected) FP32 GEMM through the same kernels: the identity
+        # basis with all projections kept only permutes the contraction index
+        PL = 4
+        plain = pg.Basis("identity", PL)
+        Ap = torch.empty(pg.packed_bytes(M, K, PL, PL), dtype=torch.uint8, device=dev)
+        Bp = torch.empty(pg.packed_bytes(W, K, PL, PL), dtype=torch.uint8, device=dev)
         Rp = torch.empty((M, W), dtype=torch.float32, device=dev)
 
         def pstep():
-            pg.pack_a(Ad, 1, plain, out=Ap)
-            pg.pack_b(Bd, 1, plain, transB=True, out=Bp)
-            pg.gemm_packed(Ap, Bp, 1, M, W, K, 1, 1, 1, out=Rp)
+            pg.pack_a(Ad, PL, plain, out=Ap)
+            pg.pack_b(Bd, PL, plain, transB=True, out=Bp)
+            pg.gemm_packed(Ap, Bp, PL, M, W, K, PL, PL, PL, out=Rp)
         for _ in range(3):
             pstep()
         torch.cuda.synchronize()

@@ -146,14 +146,56 @@ int pj_pack_a(pj_basis b, int rmax, char transA, int M, int K, const void* A, in
 int pj_pack_b(pj_basis b, int rmax, char transB, int W, int K, const void* B, int64_t ldb,
               int prec, void* packed, size_t packed_bytes, void* stream);
 
+/* Packs both sides in ONE launch (same arguments as pj_pack_a and pj_pack_b
+ * together); the small side overlaps with the large one. */
+int pj_pack_ab(pj_basis b, int rmax, char transA, char transB, int M, int W, int K,
+               const void* A, int64_t lda, const void* B, int64_t ldb, int prec,
+               void* Ap, size_t a_bytes, void* Bp, size_t b_bytes, void* stream);
+
 /* R <- sum_{l<r} A_c^{(l)} B_d^{(l)} + beta R from operands packed with the
  * same (K, L, prec) at rmax_a >= r and rmax_b >= r; a_bytes and b_bytes are
  * the sizes of the two buffers (PJ_ERR_WORKSPACE if smaller than
- * pj_packed_bytes for their rmax). */
+ * pj_packed_bytes for their rmax).  tile_cfg selects the workgroup tile
+ * (0 .. pj_gemm_tile_configs() - 1), or -1 for the built-in choice. */
 int pj_gemm_packed(int r, int M, int W, int K, int L, int prec,
                    const void* Ap, int rmax_a, size_t a_bytes,
                    const void* Bp, int rmax_b, size_t b_bytes,
-                   float beta, void* R, int64_t ldr, void* stream);
+                   float beta, void* R, int64_t ldr, int tile_cfg, void* stream);
+
+/* Number of workgroup tile configurations of the reduced contraction; writes
+ * the tile sizes (rows x columns of R) of the first max_configs into tile_m,
+ * tile_n when both are non-NULL.  Used by the autotuner. */
+int pj_gemm_tile_configs(int prec, int* tile_m, int* tile_n, int max_configs);
+
+/* ------------------------------------------------- batched projected GEMM */
+
+/* One problem of a batch: R <- A Q_{r,K} B + beta R with proj_gemm's
+ * layout conventions (trans 'N' / 'T', row-major, leading dimensions). */
+typedef struct {
+    int M, W, K;
+    char transA, transB;
+    const void* A; int64_t lda;
+    const void* B; int64_t ldb;
+    void* R; int64_t ldr;
+} pj_gemm_desc;
+
+/* Bytes of workspace proj_gemm_batched needs (0 for invalid arguments). */
+size_t pj_gemm_batched_workspace_bytes(int count, const pj_gemm_desc* problems, int L, int r, int prec,
+                                       int tile_cfg);
+
+/* Many independent projected GEMMs of any sizes sharing one basis, r and
+ * precision (paper Sec. III-B applied to each problem): ONE launch projects
+ * and packs every A and B side, and ONE persistent launch computes every
+ * (problem, output tile) item, the items sorted by decreasing contraction
+ * length and dealt round-robin over a grid sized to the device.
+ *   problems : host array of `count` descriptors (device pointers inside).
+ *   tile_cfg : workgroup tile as in pj_gemm_packed (-1: built-in choice);
+ *              the autotuner picks it per batch.
+ * The problem and item tables (a few KB) are copied into the workspace with
+ * hipMemcpyAsync from host memory; the call returns once they are staged.
+ * Errors: any invalid descriptor rejects the whole batch before device work. */
+int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems, float beta, int prec,
+                      int tile_cfg, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------- projected cross-correlation */
 

@@ -3,6 +3,7 @@
 // work), workspace carving and kernel launches.
 #include "../../include/projgemm.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -30,7 +31,7 @@ namespace {
 constexpr int kMaxL = 256;
 
 bool valid_prec(int p) { return p >= PJ_F64 && p <= PJ_FP8X2; }
-bool implemented_prec(int p) { return p >= PJ_F64 && p <= PJ_F16X3; }
+bool implemented_prec(int p) { return p >= PJ_F64 && p <= PJ_FP8X2; }
 bool is_n(char t) { return t == 'N' || t == 'n'; }
 bool is_t(char t) { return t == 'T' || t == 't'; }
 
@@ -163,12 +164,11 @@ int check_pack(pj_basis b, int rmax, char trans, int rows, int K, const void* X,
     if ((prec == PJ_FP8 || prec == PJ_FP8X2) && rmax > 8) return PJ_ERR_UNSUPPORTED;
     if (!implemented_prec(prec)) return PJ_ERR_UNSUPPORTED;
     if (packed_bytes < (size_t)pack_geom(rows, K, b->L, rmax, prec).total) return PJ_ERR_WORKSPACE;
-    if (!b->on_device) return PJ_ERR_HIP;
     return PJ_OK;
 }
 
-int do_pack(pj_basis b, int rmax, bool a_side, char trans, int rows, int K, const void* X, int64_t ld,
-            int prec, void* packed, void* stream)
+PackArgs pack_args(pj_basis b, int rmax, bool a_side, char trans, int rows, int K, const void* X, int64_t ld,
+                   int prec, void* packed)
 {
     PackArgs a;
     a.X = X;
@@ -185,9 +185,22 @@ int do_pack(pj_basis b, int rmax, bool a_side, char trans, int rows, int K, cons
     else a.coef = a_side ? (const void*)b->Cf : (const void*)b->DTf;
     a.out = packed;
     a.geom = pack_geom(rows, K, b->L, rmax, prec);
-    if (a.geom.Gp / layout_of(prec).KB > 65535 || a.geom.nrb > 0x7fffffff) return PJ_ERR_UNSUPPORTED;
-    int rc = launch_pack(prec, a, (hipStream_t)stream);
+    return a;
+}
+
+int run_pack(int prec, const PackArgs* a, int n, void* stream)
+{
+    for (int i = 0; i < n; ++i)
+        if (a[i].geom.nrb * (a[i].geom.Gp / layout_of(prec).KB) > 0x3fffffff) return PJ_ERR_UNSUPPORTED;
+    int rc = launch_pack_n(prec, a, n, (hipStream_t)stream);
     return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
+}
+
+int do_pack(pj_basis b, int rmax, bool a_side, char trans, int rows, int K, const void* X, int64_t ld,
+            int prec, void* packed, void* stream)
+{
+    PackArgs a = pack_args(b, rmax, a_side, trans, rows, K, X, ld, prec, packed);
+    return run_pack(prec, &a, 1, stream);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -285,6 +298,7 @@ int pj_pack_a(pj_basis b, int rmax, char transA, int M, int K, const void* A, in
 {
     int rc = check_pack(b, rmax, transA, M, K, A, lda, prec, packed, packed_bytes);
     if (rc != PJ_OK) return rc;
+    if (!b->on_device) return PJ_ERR_HIP;
     return do_pack(b, rmax, true, transA, M, K, A, lda, prec, packed, stream);
 }
 
@@ -297,11 +311,38 @@ int pj_pack_b(pj_basis b, int rmax, char transB, int W, int K, const void* B, in
     if (W >= 1 && K >= 1 && ldb < (is_n(transB) ? (int64_t)W : (int64_t)K)) return PJ_ERR_SHAPE;
     int rc = check_pack(b, rmax, is_n(transB) ? 'T' : 'N', W, K, B, ldb, prec, packed, packed_bytes);
     if (rc != PJ_OK) return rc;
+    if (!b->on_device) return PJ_ERR_HIP;
     return do_pack(b, rmax, false, transB, W, K, B, ldb, prec, packed, stream);
 }
 
+int pj_gemm_tile_configs(int prec, int* tile_m, int* tile_n, int max_configs)
+{
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    const int n = gemm_num_configs();
+    for (int i = 0; i < n && i < max_configs; ++i)
+        if (tile_m && tile_n) gemm_config_tile(prec, i, &tile_m[i], &tile_n[i]);
+    return n;
+}
+
+int pj_pack_ab(pj_basis b, int rmax, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
+               const void* B, int64_t ldb, int prec, void* Ap, size_t a_bytes, void* Bp, size_t b_bytes,
+               void* stream)
+{
+    if (!b || !B || !Bp) return PJ_ERR_ARG;
+    if (!is_n(transB) && !is_t(transB)) return PJ_ERR_ARG;
+    int rc = check_pack(b, rmax, transA, M, K, A, lda, prec, Ap, a_bytes);
+    if (rc != PJ_OK) return rc;
+    rc = check_pack(b, rmax, is_n(transB) ? 'T' : 'N', W, K, B, ldb, prec, Bp, b_bytes);
+    if (rc != PJ_OK) return rc;
+    if (!b->on_device) return PJ_ERR_HIP;
+    PackArgs pa[2] = {pack_args(b, rmax, true, transA, M, K, A, lda, prec, Ap),
+                      pack_args(b, rmax, false, transB, W, K, B, ldb, prec, Bp)};
+    return run_pack(prec, pa, 2, stream);
+}
+
 int pj_gemm_packed(int r, int M, int W, int K, int L, int prec, const void* Ap, int rmax_a, size_t a_bytes,
-                   const void* Bp, int rmax_b, size_t b_bytes, float beta, void* R, int64_t ldr, void* stream)
+                   const void* Bp, int rmax_b, size_t b_bytes, float beta, void* R, int64_t ldr, int tile_cfg,
+                   void* stream)
 {
     if (!Ap || !Bp || !R) return PJ_ERR_ARG;
     if (!valid_prec(prec)) return PJ_ERR_ARG;
@@ -325,7 +366,8 @@ int pj_gemm_packed(int r, int M, int W, int K, int L, int prec, const void* Ap, 
     g.R = R;
     g.ldr = ldr;
     g.beta = beta;
-    int rc = launch_gemm(prec, g, (hipStream_t)stream);
+    if (tile_cfg >= gemm_num_configs()) return PJ_ERR_ARG;
+    int rc = launch_gemm(prec, g, tile_cfg, (hipStream_t)stream);
     return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
 }
 
@@ -348,12 +390,146 @@ int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, 
     if (!b->on_device) return PJ_ERR_HIP;
     char* wa = (char*)ws;
     char* wb = wa + align256(pj_packed_bytes(M, K, b->L, r, prec));
-    int rc = do_pack(b, r, true, transA, M, K, A, lda, prec, wa, stream);
-    if (rc != PJ_OK) return rc;
-    rc = do_pack(b, r, false, transB, W, K, B, ldb, prec, wb, stream);
+    PackArgs pa[2] = {pack_args(b, r, true, transA, M, K, A, lda, prec, wa),
+                      pack_args(b, r, false, transB, W, K, B, ldb, prec, wb)};
+    int rc = run_pack(prec, pa, 2, stream);
     if (rc != PJ_OK) return rc;
     return pj_gemm_packed(r, M, W, K, b->L, prec, wa, r, pj_packed_bytes(M, K, b->L, r, prec), wb, r,
-                          pj_packed_bytes(W, K, b->L, r, prec), beta, R, ldr, stream);
+                          pj_packed_bytes(W, K, b->L, r, prec), beta, R, ldr, -1, stream);
+}
+
+// ---------------------------------------------------------------- batched
+
+namespace {
+
+struct BatchPlan {
+    size_t pack_table, probs_off, items_off, ops_off, total;
+    std::vector<size_t> a_off, b_off;
+    int64_t nitems;
+    int cfg;
+};
+
+int check_desc(const pj_gemm_desc& d)
+{
+    if (!d.A || !d.B || !d.R) return PJ_ERR_ARG;
+    if ((!is_n(d.transA) && !is_t(d.transA)) || (!is_n(d.transB) && !is_t(d.transB))) return PJ_ERR_ARG;
+    if (d.M < 1 || d.W < 1 || d.K < 1) return PJ_ERR_SHAPE;
+    if (d.lda < (is_n(d.transA) ? (int64_t)d.K : (int64_t)d.M)) return PJ_ERR_SHAPE;
+    if (d.ldb < (is_n(d.transB) ? (int64_t)d.W : (int64_t)d.K)) return PJ_ERR_SHAPE;
+    if (d.ldr < d.W) return PJ_ERR_SHAPE;
+    return PJ_OK;
+}
+
+int plan_batch(int count, const pj_gemm_desc* p, int L, int r, int prec, int tile_cfg, BatchPlan& bp)
+{
+    if (count < 1 || !p) return PJ_ERR_ARG;
+    if (L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return PJ_ERR_ARG;
+    if (tile_cfg >= gemm_num_configs()) return PJ_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        int rc = check_desc(p[i]);
+        if (rc != PJ_OK) return rc;
+    }
+    if ((prec == PJ_FP8 || prec == PJ_FP8X2) && r > 8) return PJ_ERR_UNSUPPORTED;
+    bp.cfg = tile_cfg;
+    if (bp.cfg < 0) bp.cfg = 0;
+    int tm = 0, tn = 0;
+    gemm_config_tile(prec, bp.cfg, &tm, &tn);
+    bp.nitems = 0;
+    bp.a_off.resize(count);
+    bp.b_off.resize(count);
+    size_t off = 0;
+    bp.pack_table = rup((int64_t)pack_grouped_table_bytes(2 * count), 256);
+    off += bp.pack_table;
+    bp.probs_off = off;
+    off += rup((int64_t)sizeof(GroupedProblem) * count, 256);
+    for (int i = 0; i < count; ++i) bp.nitems += cdiv(p[i].M, tm) * cdiv(p[i].W, tn);
+    bp.items_off = off;
+    off += rup((int64_t)sizeof(GroupedItem) * bp.nitems, 256);
+    bp.ops_off = off;
+    for (int i = 0; i < count; ++i) {
+        bp.a_off[i] = off;
+        off += align256(pj_packed_bytes(p[i].M, p[i].K, L, r, prec));
+        bp.b_off[i] = off;
+        off += align256(pj_packed_bytes(p[i].W, p[i].K, L, r, prec));
+    }
+    bp.total = off;
+    return PJ_OK;
+}
+
+int device_cus()
+{
+    static int cached = 0;
+    if (cached > 0) return cached;
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        n = 256;
+    cached = n;
+    return n;
+}
+
+}  // namespace
+
+size_t pj_gemm_batched_workspace_bytes(int count, const pj_gemm_desc* problems, int L, int r, int prec,
+                                       int tile_cfg)
+{
+    BatchPlan bp;
+    if (plan_batch(count, problems, L, r, prec, tile_cfg, bp) != PJ_OK) return 0;
+    return bp.total;
+}
+
+int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems, float beta, int prec,
+                      int tile_cfg, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!b) return PJ_ERR_ARG;
+    BatchPlan bp;
+    int rc = plan_batch(count, problems, b->L, r, prec, tile_cfg, bp);
+    if (rc != PJ_OK) return rc;
+    if (!ws || ws_bytes < bp.total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)ws;
+    const Layout ly = layout_of(prec);
+    std::vector<PackArgs> pa(2 * (size_t)count);
+    std::vector<GroupedProblem> gp(count);
+    int tm = 0, tn = 0;
+    gemm_config_tile(prec, bp.cfg, &tm, &tn);
+    std::vector<GroupedItem> items;
+    items.reserve(bp.nitems);
+    for (int i = 0; i < count; ++i) {
+        const pj_gemm_desc& d = problems[i];
+        pa[2 * i] = pack_args(b, r, true, d.transA, d.M, d.K, d.A, d.lda, prec, w + bp.a_off[i]);
+        pa[2 * i + 1] = pack_args(b, r, false, d.transB, d.W, d.K, d.B, d.ldb, prec, w + bp.b_off[i]);
+        const PackGeom& ga = pa[2 * i].geom;
+        const PackGeom& gb = pa[2 * i + 1].geom;
+        GroupedProblem& g = gp[i];
+        g.X = w + bp.a_off[i]; g.x_nrb = ga.nrb; g.x_nkb = ga.nkb;
+        g.x_plane = ga.plane_bytes + ga.scale_plane; g.x_pb = ga.plane_bytes;
+        g.Y = w + bp.b_off[i]; g.y_nrb = gb.nrb; g.y_nkb = gb.nkb;
+        g.y_plane = gb.plane_bytes + gb.scale_plane; g.y_pb = gb.plane_bytes;
+        g.nkb = (int64_t)r * ga.Gp / ly.KB;
+        g.P = d.M; g.Q = d.W; g.R = d.R; g.ldr = d.ldr; g.beta = beta;
+        const int64_t ntm = cdiv(d.M, tm), ntn = cdiv(d.W, tn);
+        for (int64_t y = 0; y < ntn; ++y)
+            for (int64_t x = 0; x < ntm; ++x) items.push_back(GroupedItem{i, (int32_t)x, (int32_t)y});
+    }
+    // longest contractions first (stable: problem order, then tile order)
+    std::stable_sort(items.begin(), items.end(), [&](const GroupedItem& u, const GroupedItem& v) {
+        return gp[u.prob].nkb > gp[v.prob].nkb;
+    });
+    for (const PackArgs& x : pa)
+        if (x.geom.nrb * (x.geom.Gp / ly.KB) > 0x3fffffff) return PJ_ERR_UNSUPPORTED;
+    rc = launch_pack_grouped(prec, pa.data(), 2 * count, w, st);
+    if (rc != 0) return rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP;
+    if (hipMemcpyAsync(w + bp.probs_off, gp.data(), sizeof(GroupedProblem) * count, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(w + bp.items_off, items.data(), sizeof(GroupedItem) * items.size(), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        return PJ_ERR_HIP;
+    const int64_t grid = std::min<int64_t>(bp.nitems, 2 * (int64_t)device_cus());
+    rc = launch_gemm_grouped(prec, (const GroupedProblem*)(w + bp.probs_off), (const GroupedItem*)(w + bp.items_off),
+                             bp.nitems, grid, bp.cfg, st);
+    return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
 }
 
 size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec)

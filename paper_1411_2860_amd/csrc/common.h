@@ -24,6 +24,10 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_F16 = 4, P_F16X3 =
 //
 // Tiles are stored [plane][row_block][k_block][lane][LB], then, for FP8,
 // one E8M0 scale byte per lane per tile: [plane][row_block][k_block][lane].
+// FP8 is the exception to the lane rule above: the block-scaled 8-bit
+// instruction takes 64-index tiles whose MX block h (32 indices, one scale)
+// of a row is split over bytes 16h..16h+15 of lanes row and 32 + row; the
+// scale of block h comes from lane 32h + row.
 //
 // Projected operands use the contraction order k = l * Gp + j (projection
 // major, group j < G zero-padded up to Gp = roundup(G, KB)), so the first
@@ -110,6 +114,12 @@ struct PackArgs {
     PackGeom geom;
 };
 int launch_pack(int prec, const PackArgs& a, hipStream_t s);
+// Packs n (1 or 2) operands of the same precision in one launch.
+int launch_pack_n(int prec, const PackArgs* a, int n, hipStream_t s);
+// Packs any number of operands in one launch, driven by a job table that is
+// copied into `table` (device memory of pack_grouped_table_bytes(n) bytes).
+size_t pack_grouped_table_bytes(int n);
+int launch_pack_grouped(int prec, const PackArgs* a, int n, void* table, hipStream_t s);
 
 struct GemmArgs {
     const void* X; PackGeom gx;  // P rows
@@ -119,7 +129,26 @@ struct GemmArgs {
     void* R; int64_t ldr;        // P x Q row-major, float (double for F64)
     float beta;
 };
-int launch_gemm(int prec, const GemmArgs& a, hipStream_t s);
+// One problem of a grouped launch, as stored in device memory.
+struct GroupedProblem {
+    const void* X; int64_t x_nrb, x_nkb, x_plane, x_pb;
+    const void* Y; int64_t y_nrb, y_nkb, y_plane, y_pb;
+    int64_t nkb, P, Q;
+    void* R; int64_t ldr;
+    float beta;
+};
+struct GroupedItem {
+    int32_t prob;
+    int32_t tm, tn;
+};
+int launch_gemm_grouped(int prec, const GroupedProblem* probs, const GroupedItem* items, int64_t nitems,
+                        int64_t grid, int cfg, hipStream_t s);
+
+// cfg < 0 picks the default tile configuration for the shape.
+int launch_gemm(int prec, const GemmArgs& a, int cfg, hipStream_t s);
+int gemm_num_configs();
+int gemm_config_tile(int prec, int cfg, int* tile_m, int* tile_n);
+int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb);
 
 // Projected cross-correlation (conv.hip).
 struct ConvGeom {

@@ -21,11 +21,20 @@ namespace {
 // ---- MFMA operand traits ----------------------------------------------------
 template <int PREC> struct MT;
 
+// Plain 16-byte lane vectors.
+template <typename F>
+__device__ inline F load_plain(const char* plane, int64_t plane_bytes, int64_t tile, int lane)
+{
+    (void)plane_bytes;
+    return *reinterpret_cast<const F*>(plane + (tile * 64 + lane) * 16);
+}
+
 template <> struct MT<P_F32> {
     static constexpr int RB = 32, NACC = 16, PLANES = 1;
     using frag = f32x4;
     using acc = f32x16;
     using out_t = float;
+    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
     __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][0], b[0][0], c, 0, 0, 0);
@@ -40,6 +49,7 @@ template <> struct MT<P_F64> {
     using frag = f64x2;
     using acc = f64x4;
     using out_t = double;
+    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
     __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0][0], b[0][0], c, 0, 0, 0);
@@ -52,6 +62,7 @@ template <> struct MT<P_BF16> {
     using frag = bf16x8;
     using acc = f32x16;
     using out_t = float;
+    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
     __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], c, 0, 0, 0);
@@ -63,6 +74,7 @@ template <> struct MT<P_BF16X3> {
     using frag = bf16x8;
     using acc = f32x16;
     using out_t = float;
+    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
     __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], c, 0, 0, 0);
@@ -76,6 +88,7 @@ template <> struct MT<P_F16> {
     using frag = f16x8;
     using acc = f32x16;
     using out_t = float;
+    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
     __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[0], b[0], c, 0, 0, 0);
@@ -87,11 +100,54 @@ template <> struct MT<P_F16X3> {
     using frag = f16x8;
     using acc = f32x16;
     using out_t = float;
+    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
     __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[1], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[0], b[1], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[0], b[0], c, 0, 0, 0);
+    }
+};
+
+// FP8: 32-byte lane vectors of OCP e4m3 codes plus one E8M0 scale byte per
+// lane (the MX scale of the 32 contraction indices the lane holds), fed to
+// the block-scaled 32 x 32 x 64 matrix instruction.
+struct Fp8Frag {
+    i32x8 v;
+    int s;
+};
+
+__device__ inline Fp8Frag load_fp8(const char* plane, int64_t plane_bytes, int64_t tile, int lane)
+{
+    Fp8Frag f;
+    f.v = *reinterpret_cast<const i32x8*>(plane + (tile * 64 + lane) * 32);
+    f.s = (int)(unsigned char)plane[plane_bytes + tile * 64 + lane];
+    return f;
+}
+
+template <> struct MT<P_FP8> {
+    static constexpr int RB = 32, NACC = 16, PLANES = 1;
+    using frag = Fp8Frag;
+    using acc = f32x16;
+    using out_t = float;
+    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_fp8(pl, pb, t, lane); }
+    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    {
+        c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[0].v, b[0].v, c, 0, 0, 0, a[0].s, 0, b[0].s);
+    }
+};
+
+template <> struct MT<P_FP8X2> {
+    static constexpr int RB = 32, NACC = 16, PLANES = 2;
+    using frag = Fp8Frag;
+    using acc = f32x16;
+    using out_t = float;
+    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_fp8(pl, pb, t, lane); }
+    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    {
+        c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[1].v, b[0].v, c, 0, 0, 0, a[1].s, 0, b[0].s);
+        c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[0].v, b[1].v, c, 0, 0, 0, a[0].s, 0, b[1].s);
+        c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[0].v, b[0].v, c, 0, 0, 0, a[0].s, 0, b[0].s);
     }
 };
 
@@ -118,39 +174,37 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t n)
     return x * q + (x < rem ? x : rem) + i;
 }
 
+// One workgroup tile (tm, tn) of R = X Y^T: the body shared by the single
+// and the grouped (persistent) launches.
 template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
-    const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane,
-    const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane,
+__device__ inline void gemm_tile(
+    const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
+    const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
     int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
-    float beta, int64_t tiles_m, int64_t ntiles)
+    float beta, int64_t tm, int64_t tn)
 {
     using T = MT<PREC>;
     using frag = typename T::frag;
     using acc_t = typename T::acc;
     constexpr int RB = T::RB, PL = T::PLANES;
-    constexpr int64_t TB = 64 * 16;   // bytes per tile per plane
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave % WAVES_M, wn = wave / WAVES_M;
-    const int64_t tile = xcd_remap(blockIdx.x, ntiles);
-    const int64_t tm = tile % tiles_m, tn = tile / tiles_m;
     const int64_t rb0 = (tm * WAVES_M + wm) * WM;
     const int64_t cb0 = (tn * WAVES_N + wn) * WN;
 
-    const char* xp[WM];
-    const char* yp[WN];
+    int64_t xt[WM], yt[WN];   // first tile index of each row block
     bool xv[WM], yv[WN];
 #pragma unroll
     for (int a = 0; a < WM; ++a) {
         xv[a] = rb0 + a < x_nrb;
-        xp[a] = X + ((xv[a] ? rb0 + a : 0) * x_nkb * 64 + lane) * 16;
+        xt[a] = (xv[a] ? rb0 + a : 0) * x_nkb;
     }
 #pragma unroll
     for (int b = 0; b < WN; ++b) {
         yv[b] = cb0 + b < y_nrb;
-        yp[b] = Y + ((yv[b] ? cb0 + b : 0) * y_nkb * 64 + lane) * 16;
+        yt[b] = (yv[b] ? cb0 + b : 0) * y_nkb;
     }
 
     acc_t acc[WM][WN];
@@ -167,12 +221,12 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
         for (int a = 0; a < WM; ++a)
 #pragma unroll
             for (int pl = 0; pl < PL; ++pl)
-                xf[a][pl] = xv[a] ? *reinterpret_cast<const frag*>(xp[a] + pl * x_plane + kb * TB) : frag{};
+                xf[a][pl] = xv[a] ? T::load(X + pl * x_plane, x_pb, xt[a] + kb, lane) : frag{};
 #pragma unroll
         for (int b = 0; b < WN; ++b)
 #pragma unroll
             for (int pl = 0; pl < PL; ++pl)
-                yf[b][pl] = yv[b] ? *reinterpret_cast<const frag*>(yp[b] + pl * y_plane + kb * TB) : frag{};
+                yf[b][pl] = yv[b] ? T::load(Y + pl * y_plane, y_pb, yt[b] + kb, lane) : frag{};
     };
 
     // The contraction runs from the last k-block to the first, i.e. from the
@@ -218,6 +272,34 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
 }
 
 template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
+    const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
+    const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
+    int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
+    float beta, int64_t tiles_m, int64_t ntiles)
+{
+    const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+    gemm_tile<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb, nkb, P,
+                                              Q, R, ldr, beta, tile % tiles_m, tile / tiles_m);
+}
+
+// Persistent grouped launch: workgroup b processes items b, b + grid, ... of
+// a list of (problem, tile) items sorted by decreasing contraction length, so
+// the longest tiles start first and the tail is made of short ones.
+template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_grouped_kernel(
+    const GroupedProblem* __restrict__ probs, const GroupedItem* __restrict__ items, int64_t nitems)
+{
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const GroupedItem w = items[it];
+        const GroupedProblem& p = probs[w.prob];
+        gemm_tile<PREC, WM, WN, WAVES_M, WAVES_N>(
+            (const char*)p.X, p.x_nrb, p.x_nkb, p.x_plane, p.x_pb, (const char*)p.Y, p.y_nrb, p.y_nkb, p.y_plane,
+            p.y_pb, p.nkb, p.P, p.Q, (typename MT<PREC>::out_t*)p.R, p.ldr, p.beta, w.tm, w.tn);
+    }
+}
+
+template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 int launch_gemm_t(const GemmArgs& a, hipStream_t s)
 {
     constexpr int RB = MT<PREC>::RB;
@@ -227,23 +309,119 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     (void)RB;
     hipLaunchKernelGGL((gemm_kernel<PREC, WM, WN, WAVES_M, WAVES_N>), dim3((unsigned)ntiles),
                        dim3(64 * WAVES_M * WAVES_N), 0, s,
-                       (const char*)a.X, a.gx.nrb, a.gx.nkb, a.gx.plane_bytes + a.gx.scale_plane,
-                       (const char*)a.Y, a.gy.nrb, a.gy.nkb, a.gy.plane_bytes + a.gy.scale_plane,
+                       (const char*)a.X, a.gx.nrb, a.gx.nkb, a.gx.plane_bytes + a.gx.scale_plane, a.gx.plane_bytes,
+                       (const char*)a.Y, a.gy.nrb, a.gy.nkb, a.gy.plane_bytes + a.gy.scale_plane, a.gy.plane_bytes,
                        a.nkb, a.P, a.Q, (typename MT<PREC>::out_t*)a.R, a.ldr, a.beta, tiles_m, ntiles);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace
 
-int launch_gemm(int prec, const GemmArgs& a, hipStream_t s)
+// Tile configurations: (MFMA blocks per wave along M, along N, waves along M,
+// waves along N).  The workgroup tile is RB*WM*WAVES_M x RB*WN*WAVES_N.
+#define PJ_GEMM_CONFIGS(X) \
+    X(0, 2, 2, 2, 2)       \
+    X(1, 4, 2, 2, 2)       \
+    X(2, 2, 4, 2, 2)       \
+    X(3, 4, 4, 2, 2)       \
+    X(4, 2, 2, 1, 1)       \
+    X(5, 4, 4, 1, 1)       \
+    X(6, 1, 1, 2, 2)
+
+namespace {
+struct TileCfg { int wm, wn, wavm, wavn; };
+constexpr TileCfg kTileCfgs[] = {
+#define PJ_CFG_ROW(i, a, b, c, d) {a, b, c, d},
+    PJ_GEMM_CONFIGS(PJ_CFG_ROW)
+#undef PJ_CFG_ROW
+};
+constexpr int kNumTileCfgs = (int)(sizeof(kTileCfgs) / sizeof(kTileCfgs[0]));
+
+template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+int launch_grouped_t(const GroupedProblem* probs, const GroupedItem* items, int64_t nitems, int64_t grid,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL((gemm_grouped_kernel<PREC, WM, WN, WAVES_M, WAVES_N>), dim3((unsigned)grid),
+                       dim3(64 * WAVES_M * WAVES_N), 0, s, probs, items, nitems);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int PREC>
+int launch_grouped_cfg(const GroupedProblem* probs, const GroupedItem* items, int64_t nitems, int64_t grid, int cfg,
+                       hipStream_t s)
+{
+    switch (cfg) {
+#define PJ_CFG_CASE(i, a_, b_, c_, d_) \
+    case i: return launch_grouped_t<PREC, a_, b_, c_, d_>(probs, items, nitems, grid, s);
+        PJ_GEMM_CONFIGS(PJ_CFG_CASE)
+#undef PJ_CFG_CASE
+    default: return -2;
+    }
+}
+
+template <int PREC>
+int launch_cfg(const GemmArgs& a, int cfg, hipStream_t s)
+{
+    switch (cfg) {
+#define PJ_CFG_CASE(i, a_, b_, c_, d_) \
+    case i: return launch_gemm_t<PREC, a_, b_, c_, d_>(a, s);
+        PJ_GEMM_CONFIGS(PJ_CFG_CASE)
+#undef PJ_CFG_CASE
+    default: return -2;
+    }
+}
+}  // namespace
+
+int gemm_num_configs() { return kNumTileCfgs; }
+
+int launch_gemm_grouped(int prec, const GroupedProblem* probs, const GroupedItem* items, int64_t nitems,
+                        int64_t grid, int cfg, hipStream_t s)
 {
     switch (prec) {
-    case P_F64:    return launch_gemm_t<P_F64, 4, 4, 2, 2>(a, s);
-    case P_F32:    return launch_gemm_t<P_F32, 2, 2, 2, 2>(a, s);
-    case P_BF16:   return launch_gemm_t<P_BF16, 2, 2, 2, 2>(a, s);
-    case P_BF16X3: return launch_gemm_t<P_BF16X3, 2, 2, 2, 2>(a, s);
-    case P_F16:    return launch_gemm_t<P_F16, 2, 2, 2, 2>(a, s);
-    case P_F16X3:  return launch_gemm_t<P_F16X3, 2, 2, 2, 2>(a, s);
+    case P_F64:    return launch_grouped_cfg<P_F64>(probs, items, nitems, grid, cfg, s);
+    case P_F32:    return launch_grouped_cfg<P_F32>(probs, items, nitems, grid, cfg, s);
+    case P_BF16:   return launch_grouped_cfg<P_BF16>(probs, items, nitems, grid, cfg, s);
+    case P_BF16X3: return launch_grouped_cfg<P_BF16X3>(probs, items, nitems, grid, cfg, s);
+    case P_F16:    return launch_grouped_cfg<P_F16>(probs, items, nitems, grid, cfg, s);
+    case P_F16X3:  return launch_grouped_cfg<P_F16X3>(probs, items, nitems, grid, cfg, s);
+    case P_FP8:    return launch_grouped_cfg<P_FP8>(probs, items, nitems, grid, cfg, s);
+    case P_FP8X2:  return launch_grouped_cfg<P_FP8X2>(probs, items, nitems, grid, cfg, s);
+    default:       return -2;
+    }
+}
+
+int gemm_config_tile(int prec, int cfg, int* tile_m, int* tile_n)
+{
+    if (cfg < 0 || cfg >= kNumTileCfgs) return -1;
+    const int rb = layout_of(prec).RB;
+    *tile_m = rb * kTileCfgs[cfg].wm * kTileCfgs[cfg].wavm;
+    *tile_n = rb * kTileCfgs[cfg].wn * kTileCfgs[cfg].wavn;
+    return 0;
+}
+
+int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
+{
+    (void)nkb;
+    if (prec == P_F64) return 3;
+    // small problems: smaller tiles so that the grid still covers the chip
+    const int64_t tiles128 = cdiv(P, 128) * cdiv(Q, 128);
+    if (tiles128 < 256) return 6;
+    if (prec == P_F32 || prec == P_BF16X3 || prec == P_F16X3) return 2;   // 128 x 256
+    return 0;
+}
+
+int launch_gemm(int prec, const GemmArgs& a, int cfg, hipStream_t s)
+{
+    if (cfg < 0) cfg = gemm_default_config(prec, a.P, a.Q, a.nkb);
+    switch (prec) {
+    case P_F64:    return launch_cfg<P_F64>(a, cfg, s);
+    case P_F32:    return launch_cfg<P_F32>(a, cfg, s);
+    case P_BF16:   return launch_cfg<P_BF16>(a, cfg, s);
+    case P_BF16X3: return launch_cfg<P_BF16X3>(a, cfg, s);
+    case P_F16:    return launch_cfg<P_F16>(a, cfg, s);
+    case P_F16X3:  return launch_cfg<P_F16X3>(a, cfg, s);
+    case P_FP8:    return launch_cfg<P_FP8>(a, cfg, s);
+    case P_FP8X2:  return launch_cfg<P_FP8X2>(a, cfg, s);
     default:       return -2;
     }
 }

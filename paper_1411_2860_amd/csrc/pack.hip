@@ -11,10 +11,17 @@
 //
 // One workgroup owns RB source rows (one row block of the packed operand) and
 // KB consecutive groups j (one k-block per projection), for every projection
-// l < r.  The source tile is staged through LDS in chunks of TC indices t;
-// lane (row, g) accumulates E consecutive groups for RL projections per
-// chunk of work, with the coefficients read as wave-uniform scalars.  Each
+// l < r.  The source tile is staged through LDS in chunks of TC indices t,
+// laid out [row][group][t] with padded strides so that the 16-byte LDS reads
+// of a wavefront spread evenly over the banks.  Lane (row, g) accumulates the
+// E consecutive groups of its lane vector for RL projections at a time; the
+// coefficients are wave-uniform scalars, each used for 4 t x E groups.  Every
 // wave writes whole 64-lane tiles, so stores are fully coalesced.
+//
+// Both operands of a GEMM can be packed by ONE launch (two jobs over one
+// grid), so the small A side overlaps with the large B side.
+#include <vector>
+
 #include "common.h"
 
 namespace pj {
@@ -22,15 +29,81 @@ namespace pj {
 namespace {
 
 constexpr int kPackThreads = 256;
-constexpr int kPackLdsBytes = 60 * 1024;
+constexpr int kPackLdsBytes = 48 * 1024;
 
-template <typename T>
-__device__ inline T ld_src(const T* __restrict__ X, int64_t idx) { return X[idx]; }
+template <typename TIn>
+struct PackJob {
+    const TIn* X;
+    int64_t ld;
+    int trans;       // 0: (p, k) at X[p*ld + k]; 1: at X[k*ld + p]
+    int vec4;        // 16-byte loads allowed (k-contiguous and aligned)
+    int64_t P, K;
+    int L, r;
+    const TIn* coef; // L x L, element (t, l)
+    char* out;
+    int64_t nkb, Gp, plane_stride, plane_bytes;
+    int64_t nrb, ngt;   // row blocks, group tiles (Gp / KB)
+    int TC, TCp, JS, RS;
+};
+
+// ---- OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits,
+// largest finite 448, no infinities) with round-to-nearest-even; |v| <= 448.
+__device__ inline unsigned fp8_e4m3_rne(float v)
+{
+    const unsigned sign = (__float_as_uint(v) >> 24) & 0x80u;
+    const float a = fabsf(v);
+    unsigned code;
+    if (a < 0.015625f) {                       // below 2^-6: subnormal steps of 2^-9
+        code = (unsigned)__float2uint_rn(a * 512.0f);   // 0 .. 8 (8 = smallest normal)
+    } else {
+        unsigned b = __float_as_uint(a);
+        b += 0x7FFFFu + ((b >> 20) & 1u);      // round the 23-bit mantissa to 3 bits
+        code = ((((b >> 23) & 0xFFu) - 120u) << 3) | ((b >> 20) & 7u);
+    }
+    return sign | code;
+}
+
+// Quantises 32 values to FP8 with one power-of-two (E8M0) scale 2^e chosen
+// so that the largest magnitude lands in (224, 448]; returns the scale byte
+// e + 127 and writes the 32 codes into w.
+template <typename TIn>
+__device__ inline unsigned quant_block32(const TIn* v, i32x8& w, float* deq)
+{
+    float amax = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 32; ++e) amax = fmaxf(amax, fabsf((float)v[e]));
+    int ex = -127;
+    if (amax > 0.0f) {
+        int f;
+        const float m = frexpf(amax / 448.0f, &f);   // amax / 448 = m 2^f, m in [0.5, 1)
+        ex = (m == 0.5f) ? f - 1 : f;                  // ceil(log2(amax / 448))
+        ex = ex < -127 ? -127 : (ex > 127 ? 127 : ex);
+    }
+    const float inv = ldexpf(1.0f, -ex), sc = ldexpf(1.0f, ex);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        unsigned word = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float x = (float)v[4 * d + q] * inv;
+            const unsigned c = fp8_e4m3_rne(fminf(fmaxf(x, -448.0f), 448.0f));
+            word |= c << (8 * q);
+            if (deq) {
+                const unsigned mag = c & 0x7Fu;
+                const float val = (mag < 8u) ? (float)mag * 0.001953125f
+                                             : ldexpf(1.0f + (float)(mag & 7u) * 0.125f, (int)(mag >> 3) - 7);
+                deq[4 * d + q] = ((c & 0x80u) ? -val : val) * sc;
+            }
+        }
+        w[d] = (int)word;
+    }
+    return (unsigned)(ex + 127);
+}
 
 // ---- conversion of E accumulated values into one lane vector -------------
 
 template <int PREC, int E, typename TIn>
-__device__ inline void store_lane(char* __restrict__ out, int64_t off, int64_t plane_stride,
+__device__ inline void store_lane(char* __restrict__ out, int64_t off, int64_t plane_stride, int64_t plane_bytes,
                                   const TIn (&v)[E])
 {
     if constexpr (PREC == P_F64) {
@@ -65,32 +138,61 @@ __device__ inline void store_lane(char* __restrict__ out, int64_t off, int64_t p
         }
         *reinterpret_cast<f16x8*>(out + off) = hi;
         if constexpr (PREC == P_F16X3) *reinterpret_cast<f16x8*>(out + plane_stride + off) = lo;
+    } else if constexpr (PREC == P_FP8 || PREC == P_FP8X2) {
+        static_assert(E == 32, "fp8 lane vector");
+        // The block-scaled 8-bit matrix instruction reads, for row `row` of a
+        // 64-index tile, MX block h (indices 32h .. 32h+31) as bytes 16h..16h+15
+        // of lane `row` followed by bytes 16h..16h+15 of lane 32 + row, and
+        // takes its scale from lane 32h + row.  The thread of lane (g, row)
+        // holds exactly block g, so it quantises its 32 values with one scale
+        // and scatters them as two 16-byte halves.
+        const int64_t tile = off / (64 * 32);
+        const int lane = (int)(off / 32 % 64);
+        const int g = lane / 32, row = lane % 32;
+        const int64_t lo_half = (tile * 64 + row) * 32 + 16 * g;
+        const int64_t hi_half = (tile * 64 + 32 + row) * 32 + 16 * g;
+        i32x8 w;
+        float deq[32];
+        const unsigned s = quant_block32<TIn>(v, w, PREC == P_FP8X2 ? deq : nullptr);
+        *reinterpret_cast<i32x4*>(out + lo_half) = i32x4{w[0], w[1], w[2], w[3]};
+        *reinterpret_cast<i32x4*>(out + hi_half) = i32x4{w[4], w[5], w[6], w[7]};
+        out[plane_bytes + tile * 64 + lane] = (char)s;
+        if constexpr (PREC == P_FP8X2) {
+            float res[32];
+#pragma unroll
+            for (int e = 0; e < 32; ++e) res[e] = (float)v[e] - deq[e];
+            i32x8 w2;
+            const unsigned s2 = quant_block32<float>(res, w2, nullptr);
+            *reinterpret_cast<i32x4*>(out + plane_stride + lo_half) = i32x4{w2[0], w2[1], w2[2], w2[3]};
+            *reinterpret_cast<i32x4*>(out + plane_stride + hi_half) = i32x4{w2[4], w2[5], w2[6], w2[7]};
+            out[plane_stride + plane_bytes + tile * 64 + lane] = (char)s2;
+        }
     }
 }
 
+template <typename TIn> struct Vec4;
+template <> struct Vec4<float> { using type = f32x4; };
+template <> struct Vec4<double> { using type = f64x4; };
+
 // ---- the kernel -----------------------------------------------------------
-//
-// Template parameters: TIn source type, PREC operand format, RL projections
-// per register chunk, NCH chunks per wave per pass, TRANS source layout.
-// A pass covers 4 * NCH * RL projections; passes repeat until r.
-template <typename TIn, int PREC, int RL, int NCH, bool TRANS>
-__global__ __launch_bounds__(kPackThreads) void pack_kernel(
-    const TIn* __restrict__ X, int64_t ld, int64_t P, int64_t K, int L, int r,
-    const TIn* __restrict__ coef, char* __restrict__ out, int64_t nkb, int64_t Gp,
-    int64_t plane_stride, int TC, int RS)
+template <typename TIn, int PREC, int RL, int NCH>
+__device__ inline void pack_tile(const PackJob<TIn>& J, int64_t tix)
 {
     constexpr Layout ly = layout_of(PREC);
     constexpr int TR = ly.RB, KB = ly.KB, E = ly.E;
+    using V4 = typename Vec4<TIn>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     TIn* lds = reinterpret_cast<TIn*>(smem_raw);
 
-    const int64_t rbi = blockIdx.x;
+    const int64_t rbi = tix / J.ngt;
+    const int64_t j0 = (tix % J.ngt) * KB;
     const int64_t p0 = rbi * TR;
-    const int64_t j0 = (int64_t)blockIdx.y * KB;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int row = lane % TR, g = lane / TR;
-    const int ntile = TR * KB * TC;
+    const int L = J.L, r = J.r, TC = J.TC, TCp = J.TCp, JS = J.JS, RS = J.RS;
+    const TIn* __restrict__ X = J.X;
+    const TIn* __restrict__ coef = J.coef;
 
     for (int lp = 0; lp < r; lp += 4 * NCH * RL) {
         TIn acc[NCH][RL][E];
@@ -103,43 +205,66 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(
 
         for (int t0 = 0; t0 < L; t0 += TC) {
             __syncthreads();
-            for (int idx = threadIdx.x; idx < ntile; idx += kPackThreads) {
-                int rr, jj, tt;
-                if constexpr (!TRANS) {
-                    tt = idx % TC;
-                    const int q = idx / TC;
-                    jj = q % KB;
-                    rr = q / KB;
-                } else {
-                    rr = idx % TR;
-                    const int q = idx / TR;
-                    tt = q % TC;
-                    jj = q / TC;
+            if (J.vec4) {
+                const int n4 = TR * KB * (TC / 4);
+                for (int idx = threadIdx.x; idx < n4; idx += kPackThreads) {
+                    const int tt4 = idx % (TC / 4);
+                    const int q = idx / (TC / 4);
+                    const int jj = q % KB, rr = q / KB;
+                    const int64_t p = p0 + rr;
+                    const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
+                    V4 v = {0, 0, 0, 0};
+                    if (p < J.P && k < J.K) v = *reinterpret_cast<const V4*>(X + p * J.ld + k);
+                    *reinterpret_cast<V4*>(lds + rr * RS + jj * JS + 4 * tt4) = v;
                 }
-                const int64_t p = p0 + rr;
-                const int64_t k = (j0 + jj) * L + t0 + tt;
-                TIn v = (TIn)0;
-                if (p < P && k < K) v = TRANS ? ld_src(X, k * ld + p) : ld_src(X, p * ld + k);
-                lds[rr * RS + tt * KB + jj] = v;
+            } else {
+                const int n1 = TR * KB * TCp;
+                for (int idx = threadIdx.x; idx < n1; idx += kPackThreads) {
+                    int rr, jj, tt;
+                    if (!J.trans) {
+                        tt = idx % TCp;
+                        const int q = idx / TCp;
+                        jj = q % KB;
+                        rr = q / KB;
+                    } else {
+                        rr = idx % TR;
+                        const int q = idx / TR;
+                        tt = q % TCp;
+                        jj = q / TCp;
+                    }
+                    const int64_t p = p0 + rr;
+                    const int64_t k = (j0 + jj) * L + t0 + tt;
+                    TIn v = (TIn)0;
+                    if (tt < TC && p < J.P && k < J.K) v = J.trans ? X[k * J.ld + p] : X[p * J.ld + k];
+                    lds[rr * RS + jj * JS + tt] = v;
+                }
             }
             __syncthreads();
-            for (int tt = 0; tt < TC; ++tt) {
-                TIn in[E];
-                const TIn* src = lds + row * RS + tt * KB + g * E;
-#pragma unroll
-                for (int e = 0; e < E; ++e) in[e] = src[e];
-                const int64_t crow = (int64_t)(t0 + tt) * L;
+            for (int tt4 = 0; tt4 < TCp / 4; ++tt4) {
+                const int tb = t0 + 4 * tt4;
+                TIn cf[NCH][4][RL];
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     const int lb = lp + (wave + 4 * c) * RL;
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) {
-                        if (lb + q < r) {
-                            const TIn cf = coef[crow + lb + q];
+                    for (int i = 0; i < 4; ++i)
 #pragma unroll
-                            for (int e = 0; e < E; ++e) acc[c][q][e] += in[e] * cf;
+                        for (int q = 0; q < RL; ++q)
+                            cf[c][i][q] = (tb + i < t0 + TC && lb + q < r) ? coef[(int64_t)(tb + i) * L + lb + q]
+                                                                           : (TIn)0;
+                }
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const V4 v = *reinterpret_cast<const V4*>(lds + row * RS + (g * E + e) * JS + 4 * tt4);
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) {
+                            acc[c][q][e] += v[0] * cf[c][0][q];
+                            acc[c][q][e] += v[1] * cf[c][1][q];
+                            acc[c][q][e] += v[2] * cf[c][2][q];
+                            acc[c][q][e] += v[3] * cf[c][3][q];
                         }
-                    }
                 }
             }
         }
@@ -151,62 +276,183 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(
             for (int q = 0; q < RL; ++q) {
                 const int l = lb + q;
                 if (l < r) {
-                    const int64_t kbi = ((int64_t)l * Gp + j0) / KB;
-                    const int64_t off = ((rbi * nkb + kbi) * 64 + lane) * ly.LB;
-                    store_lane<PREC, E, TIn>(out, off, plane_stride, acc[c][q]);
+                    const int64_t kbi = ((int64_t)l * J.Gp + j0) / KB;
+                    const int64_t off = ((rbi * J.nkb + kbi) * 64 + lane) * ly.LB;
+                    store_lane<PREC, E, TIn>(J.out, off, J.plane_stride, J.plane_bytes, acc[c][q]);
                 }
             }
         }
     }
 }
 
+// Two jobs passed by value (one GEMM's A and B sides).
 template <typename TIn, int PREC, int RL, int NCH>
-int launch_pack_t(const PackArgs& a, hipStream_t s)
+__global__ __launch_bounds__(kPackThreads) void pack_kernel(PackJob<TIn> ja, PackJob<TIn> jb, int64_t nblk_a)
+{
+    if ((int64_t)blockIdx.x < nblk_a) pack_tile<TIn, PREC, RL, NCH>(ja, (int64_t)blockIdx.x);
+    else pack_tile<TIn, PREC, RL, NCH>(jb, (int64_t)blockIdx.x - nblk_a);
+}
+
+// Any number of jobs from a device table; prefix[i] is the first workgroup
+// of job i (prefix[njobs] = grid size).
+template <typename TIn, int PREC, int RL, int NCH>
+__global__ __launch_bounds__(kPackThreads) void pack_grouped_kernel(const PackJob<TIn>* __restrict__ jobs,
+                                                                    const int64_t* __restrict__ prefix, int njobs)
+{
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {                 // last job whose first workgroup is <= b
+        const int mid = (lo + hi + 1) / 2;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    pack_tile<TIn, PREC, RL, NCH>(jobs[lo], b - prefix[lo]);
+}
+
+template <typename TIn, int PREC>
+PackJob<TIn> make_job(const PackArgs& a)
 {
     constexpr Layout ly = layout_of(PREC);
     const PackGeom& g = a.geom;
-    // chunk of t staged per round: a divisor of L within the LDS budget
-    int tcmax = kPackLdsBytes / (int)(ly.RB * ly.KB * sizeof(TIn));
+    PackJob<TIn> j;
+    j.X = (const TIn*)a.X;
+    j.ld = a.ld;
+    j.trans = a.trans;
+    j.vec4 = !a.trans && a.L % 4 == 0 && a.ld % 4 == 0 && a.K % 4 == 0 &&
+             ((uintptr_t)a.X % (4 * sizeof(TIn))) == 0;
+    j.P = a.P;
+    j.K = a.K;
+    j.L = a.L;
+    j.r = a.r;
+    j.coef = (const TIn*)a.coef;
+    j.out = (char*)a.out;
+    j.nkb = g.nkb;
+    j.Gp = g.Gp;
+    j.plane_stride = g.plane_bytes + g.scale_plane;
+    j.plane_bytes = g.plane_bytes;
+    j.nrb = g.nrb;
+    j.ngt = g.Gp / ly.KB;
+    // chunk of t staged per round: the largest divisor of L whose padded tile
+    // fits the LDS budget (a multiple of 4 when 16-byte loads are used)
+    auto lds_of = [&](int tc) {
+        const int tcp = (tc + 3) / 4 * 4;
+        return (size_t)ly.RB * ((size_t)ly.KB * (tcp + 4) + 4) * sizeof(TIn);
+    };
     int TC = a.L;
-    if (TC > tcmax) {
-        TC = tcmax;
-        while (a.L % TC) --TC;
-    }
-    const int RS = TC * ly.KB + 2 * ly.E;   // row stride of the LDS tile (padded)
-    const size_t lds = (size_t)ly.RB * RS * sizeof(TIn);
-    dim3 grid((unsigned)g.nrb, (unsigned)(g.Gp / ly.KB));
-    const int64_t plane_stride = g.plane_bytes + g.scale_plane;
-    if (a.trans)
-        hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH, true>), grid, dim3(kPackThreads), lds, s,
-                           (const TIn*)a.X, a.ld, a.P, a.K, a.L, a.r, (const TIn*)a.coef, (char*)a.out,
-                           g.nkb, g.Gp, plane_stride, TC, RS);
-    else
-        hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH, false>), grid, dim3(kPackThreads), lds, s,
-                           (const TIn*)a.X, a.ld, a.P, a.K, a.L, a.r, (const TIn*)a.coef, (char*)a.out,
-                           g.nkb, g.Gp, plane_stride, TC, RS);
+    while (TC > 1 && (lds_of(TC) > (size_t)kPackLdsBytes || a.L % TC != 0 || (j.vec4 && TC % 4 != 0))) --TC;
+    if (j.vec4 && TC % 4 != 0) j.vec4 = 0;
+    j.TC = TC;
+    j.TCp = (TC + 3) / 4 * 4;
+    j.JS = j.TCp + 4;
+    j.RS = ly.KB * j.JS + 4;
+    return j;
+}
+
+template <typename TIn, int PREC, int RL, int NCH>
+int launch_t(const PackArgs* a, int n, hipStream_t s)
+{
+    constexpr Layout ly = layout_of(PREC);
+    PackJob<TIn> ja = make_job<TIn, PREC>(a[0]);
+    PackJob<TIn> jb = n > 1 ? make_job<TIn, PREC>(a[1]) : ja;
+    const int64_t na = ja.nrb * ja.ngt;
+    const int64_t nb = n > 1 ? jb.nrb * jb.ngt : 0;
+    const int rs = ja.RS > jb.RS ? ja.RS : jb.RS;
+    const size_t lds = (size_t)ly.RB * rs * sizeof(TIn);
+    if (na + nb > 0x7fffffff) return -2;
+    hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH>), dim3((unsigned)(na + nb)), dim3(kPackThreads), lds, s,
+                       ja, jb, na);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename TIn, int PREC>
-int launch_pack_p(const PackArgs& a, hipStream_t s)
+int launch_p(const PackArgs* a, int n, hipStream_t s)
 {
-    constexpr int E = layout_of(PREC).E;
-    if (a.r == 1) return launch_pack_t<TIn, PREC, 1, 1>(a, s);
-    if (a.r <= 16 || E > 8) return launch_pack_t<TIn, PREC, 4, 1>(a, s);
-    return launch_pack_t<TIn, PREC, 4, 4>(a, s);
+    int r = a[0].r;
+    if (n > 1 && a[1].r > r) r = a[1].r;
+    if (r == 1) return launch_t<TIn, PREC, 1, 1>(a, n, s);
+    if constexpr (layout_of(PREC).E > 8) {
+        return launch_t<TIn, PREC, 2, 1>(a, n, s);       // FP8: r <= 8
+    } else {
+        if (r <= 16) return launch_t<TIn, PREC, 4, 1>(a, n, s);
+        return launch_t<TIn, PREC, 4, 4>(a, n, s);
+    }
+}
+
+
+template <typename TIn, int PREC, int RL, int NCH>
+int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
+{
+    constexpr Layout ly = layout_of(PREC);
+    std::vector<PackJob<TIn>> jobs(n);
+    std::vector<int64_t> prefix(n + 1, 0);
+    int rs = 0;
+    for (int i = 0; i < n; ++i) {
+        jobs[i] = make_job<TIn, PREC>(a[i]);
+        prefix[i + 1] = prefix[i] + jobs[i].nrb * jobs[i].ngt;
+        rs = jobs[i].RS > rs ? jobs[i].RS : rs;
+    }
+    if (prefix[n] > 0x7fffffff || prefix[n] == 0) return -2;
+    char* t = (char*)table;
+    const size_t jb = sizeof(PackJob<TIn>) * n;
+    if (hipMemcpyAsync(t, jobs.data(), jb, hipMemcpyHostToDevice, s) != hipSuccess) return -1;
+    if (hipMemcpyAsync(t + rup(jb, 256), prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return -1;
+    const size_t lds = (size_t)ly.RB * rs * sizeof(TIn);
+    hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH>), dim3((unsigned)prefix[n]), dim3(kPackThreads),
+                       lds, s, (const PackJob<TIn>*)t, (const int64_t*)(t + rup(jb, 256)), n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename TIn, int PREC>
+int launch_grouped_p(const PackArgs* a, int n, void* table, hipStream_t s)
+{
+    int r = 1;
+    for (int i = 0; i < n; ++i) r = a[i].r > r ? a[i].r : r;
+    if (r == 1) return launch_grouped_t<TIn, PREC, 1, 1>(a, n, table, s);
+    if constexpr (layout_of(PREC).E > 8) {
+        return launch_grouped_t<TIn, PREC, 2, 1>(a, n, table, s);
+    } else {
+        if (r <= 16) return launch_grouped_t<TIn, PREC, 4, 1>(a, n, table, s);
+        return launch_grouped_t<TIn, PREC, 4, 4>(a, n, table, s);
+    }
 }
 
 }  // namespace
 
-int launch_pack(int prec, const PackArgs& a, hipStream_t s)
+int launch_pack_n(int prec, const PackArgs* a, int n, hipStream_t s)
 {
     switch (prec) {
-    case P_F64:    return launch_pack_p<double, P_F64>(a, s);
-    case P_F32:    return launch_pack_p<float, P_F32>(a, s);
-    case P_BF16:   return launch_pack_p<float, P_BF16>(a, s);
-    case P_BF16X3: return launch_pack_p<float, P_BF16X3>(a, s);
-    case P_F16:    return launch_pack_p<float, P_F16>(a, s);
-    case P_F16X3:  return launch_pack_p<float, P_F16X3>(a, s);
+    case P_F64:    return launch_p<double, P_F64>(a, n, s);
+    case P_F32:    return launch_p<float, P_F32>(a, n, s);
+    case P_BF16:   return launch_p<float, P_BF16>(a, n, s);
+    case P_BF16X3: return launch_p<float, P_BF16X3>(a, n, s);
+    case P_F16:    return launch_p<float, P_F16>(a, n, s);
+    case P_F16X3:  return launch_p<float, P_F16X3>(a, n, s);
+    case P_FP8:    return launch_p<float, P_FP8>(a, n, s);
+    case P_FP8X2:  return launch_p<float, P_FP8X2>(a, n, s);
+    default:       return -2;
+    }
+}
+
+int launch_pack(int prec, const PackArgs& a, hipStream_t s) { return launch_pack_n(prec, &a, 1, s); }
+
+size_t pack_grouped_table_bytes(int n)
+{
+    return (size_t)rup((int64_t)sizeof(PackJob<double>) * n, 256) + (size_t)rup(8 * (int64_t)(n + 1), 256);
+}
+
+int launch_pack_grouped(int prec, const PackArgs* a, int n, void* table, hipStream_t s)
+{
+    switch (prec) {
+    case P_F64:    return launch_grouped_p<double, P_F64>(a, n, table, s);
+    case P_F32:    return launch_grouped_p<float, P_F32>(a, n, table, s);
+    case P_BF16:   return launch_grouped_p<float, P_BF16>(a, n, table, s);
+    case P_BF16X3: return launch_grouped_p<float, P_BF16X3>(a, n, table, s);
+    case P_F16:    return launch_grouped_p<float, P_F16>(a, n, table, s);
+    case P_F16X3:  return launch_grouped_p<float, P_F16X3>(a, n, table, s);
+    case P_FP8:    return launch_grouped_p<float, P_FP8>(a, n, table, s);
+    case P_FP8X2:  return launch_grouped_p<float, P_FP8X2>(a, n, table, s);
     default:       return -2;
     }
 }

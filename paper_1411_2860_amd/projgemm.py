@@ -15,8 +15,8 @@ import numpy as np
 
 __all__ = [
     "ProjGemmError", "lib", "lib_path", "Basis", "PREC", "BASIS",
-    "gemm", "pack_a", "pack_b", "gemm_packed", "packed_bytes", "gemm_workspace_bytes",
-    "conv1d", "conv1d_workspace_bytes",
+    "gemm", "pack_a", "pack_b", "pack_ab", "tile_configs", "gemm_packed", "packed_bytes", "gemm_workspace_bytes",
+    "conv1d", "conv1d_workspace_bytes", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
     "status_str",
 ]
 
@@ -60,8 +60,12 @@ _SIGNATURES = {
     "proj_gemm": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _f, _vp, _i64, _i, _vp, _sz, _vp]),
     "pj_pack_a": (_i, [_vp, _i, _ch, _i, _i, _vp, _i64, _i, _vp, _sz, _vp]),
     "pj_pack_b": (_i, [_vp, _i, _ch, _i, _i, _vp, _i64, _i, _vp, _sz, _vp]),
-    "pj_gemm_packed": (_i, [_i, _i, _i, _i, _i, _i, _vp, _i, _sz, _vp, _i, _sz, _f, _vp, _i64, _vp]),
+    "pj_gemm_packed": (_i, [_i, _i, _i, _i, _i, _i, _vp, _i, _sz, _vp, _i, _sz, _f, _vp, _i64, _i, _vp]),
+    "pj_pack_ab": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _i, _vp, _sz, _vp, _sz, _vp]),
+    "pj_gemm_tile_configs": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_i), _i]),
     "pj_conv1d_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i]),
+    "pj_gemm_batched_workspace_bytes": (_sz, [_i, _vp, _i, _i, _i, _i]),
+    "proj_gemm_batched": (_i, [_vp, _i, _i, _vp, _f, _i, _i, _vp, _sz, _vp]),
     "proj_conv1d": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
 }
 
@@ -226,8 +230,33 @@ def pack_b(B, rmax: int, basis: Basis, prec="f32", transB=False, out=None, strea
     return out
 
 
+def pack_ab(A, B, rmax: int, basis: Basis, prec="f32", transA=False, transB=False, out_a=None, out_b=None,
+            stream=None):
+    """Projects and packs both sides in one launch; returns (Ap, Bp)."""
+    p = _prec(prec)
+    M, K = (A.shape[1], A.shape[0]) if transA else tuple(A.shape)
+    W = B.shape[0] if transB else B.shape[1]
+    if out_a is None:
+        out_a = _byte_buffer(packed_bytes(M, K, basis.L, rmax, p), A.device)
+    if out_b is None:
+        out_b = _byte_buffer(packed_bytes(W, K, basis.L, rmax, p), B.device)
+    _check(lib().pj_pack_ab(basis.handle, rmax, b"T" if transA else b"N", b"T" if transB else b"N", M, W, K,
+                            _ptr(A), A.stride(0), _ptr(B), B.stride(0), p, _ptr(out_a), out_a.numel(),
+                            _ptr(out_b), out_b.numel(), _stream(stream)), "pj_pack_ab")
+    return out_a, out_b
+
+
+def tile_configs(prec="f32"):
+    """[(tile_m, tile_n)] of the reduced-contraction tile configurations."""
+    n = lib().pj_gemm_tile_configs(_prec(prec), None, None, 0)
+    tm = (_i * n)()
+    tn = (_i * n)()
+    lib().pj_gemm_tile_configs(_prec(prec), tm, tn, n)
+    return list(zip(tm, tn))
+
+
 def gemm_packed(Ap, Bp, r: int, M: int, W: int, K: int, L: int, rmax_a: int, rmax_b: int, prec="f32",
-                beta=0.0, out=None, stream=None):
+                beta=0.0, out=None, tile_cfg=-1, stream=None):
     """R = sum_{l<r} A_c^{(l)} B_d^{(l)} (+ beta R) from packed operands."""
     import torch
     p = _prec(prec)
@@ -235,7 +264,8 @@ def gemm_packed(Ap, Bp, r: int, M: int, W: int, K: int, L: int, rmax_a: int, rma
     if out is None:
         out = torch.empty((M, W), dtype=dt, device=Ap.device)
     _check(lib().pj_gemm_packed(r, M, W, K, L, p, _ptr(Ap), rmax_a, Ap.numel(), _ptr(Bp), rmax_b, Bp.numel(),
-                                float(beta), _ptr(out), out.stride(0), _stream(stream)), "pj_gemm_packed")
+                                float(beta), _ptr(out), out.stride(0), int(tile_cfg), _stream(stream)),
+           "pj_gemm_packed")
     return out
 
 
@@ -260,3 +290,48 @@ def conv1d(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, works
     _check(lib().proj_conv1d(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], Wn, _ptr(s), N, _ptr(k), _ptr(out),
                              _prec(prec), _ptr(workspace), workspace.numel(), _stream(stream)), "proj_conv1d")
     return out
+
+
+class GemmDesc(ctypes.Structure):
+    """pj_gemm_desc: one problem of a batched call."""
+    _fields_ = [("M", _i), ("W", _i), ("K", _i), ("transA", _ch), ("transB", _ch),
+                ("A", _vp), ("lda", _i64), ("B", _vp), ("ldb", _i64), ("R", _vp), ("ldr", _i64)]
+
+
+def _descs(As, Bs, Rs, transA=False, transB=False):
+    n = len(As)
+    arr = (GemmDesc * n)()
+    for i, (A, B, R) in enumerate(zip(As, Bs, Rs)):
+        M, K = (A.shape[1], A.shape[0]) if transA else tuple(A.shape)
+        W = B.shape[0] if transB else B.shape[1]
+        arr[i] = GemmDesc(M, W, K, b"T" if transA else b"N", b"T" if transB else b"N", _ptr(A), A.stride(0),
+                          _ptr(B), B.stride(0), _ptr(R), R.stride(0))
+    return arr
+
+
+def gemm_batched_workspace_bytes(descs, L: int, r: int, prec="f32", tile_cfg=-1) -> int:
+    return int(lib().pj_gemm_batched_workspace_bytes(len(descs), ctypes.cast(descs, _vp), L, r, _prec(prec),
+                                                     int(tile_cfg)))
+
+
+def gemm_batched(As, Bs, r: int, basis: Basis, prec="bf16", transA=False, transB=False, outs=None, beta=0.0,
+                 tile_cfg=-1, workspace=None, stream=None):
+    """R_i = A_i Q_{r,K_i} B_i for every problem i, in one grouped pack launch
+    and one persistent GEMM launch.  Returns the list of outputs."""
+    import torch
+    if outs is None:
+        outs = []
+        for A, B in zip(As, Bs):
+            M = A.shape[1] if transA else A.shape[0]
+            W = B.shape[0] if transB else B.shape[1]
+            outs.append(torch.empty((M, W), dtype=torch.float32, device=A.device))
+    descs = _descs(As, Bs, outs, transA, transB)
+    need = gemm_batched_workspace_bytes(descs, basis.L, r, prec, tile_cfg)
+    if need == 0:
+        raise ProjGemmError(-1, "pj_gemm_batched_workspace_bytes")
+    if workspace is None:
+        workspace = _byte_buffer(need, As[0].device)
+    _check(lib().proj_gemm_batched(basis.handle, r, len(As), ctypes.cast(descs, _vp), float(beta), _prec(prec),
+                                   int(tile_cfg), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "proj_gemm_batched")
+    return outs

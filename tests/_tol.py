@@ -19,7 +19,12 @@ import numpy as np
 
 import oracle
 
-U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11, "fp8": 2.0 ** -4}
+
+# FP8 (OCP e4m3) with one power-of-two scale 2^e per 32 values, 2^e <= amax/224:
+# values below 2^-6 * 2^e are subnormal, with absolute rounding error up to
+# 2^-10 * 2^e <= amax * 2^-10 / 224.
+FP8_SUB = 2.0 ** -10 / 224.0
 
 PREC_UNITS = {
     "f64": (U["f64"], 0.0),
@@ -28,6 +33,8 @@ PREC_UNITS = {
     "f16": (U["f32"], 2 * U["f16"]),
     "bf16x3": (U["f32"], 3 * U["bf16"] ** 2),
     "f16x3": (U["f32"], 3 * U["f16"] ** 2),
+    "fp8": (U["f32"], 2 * U["fp8"] + U["fp8"] ** 2),
+    "fp8x2": (U["f32"], 3 * U["fp8"] ** 2 + 2 * U["fp8"] ** 3),
 }
 
 
@@ -52,3 +59,18 @@ def assert_within(got, ref, bound, what=""):
         i = np.unravel_index(np.argmax(err - bound), err.shape)
         raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside bound; worst at {i}: "
                              f"got {got[i]!r} ref {ref[i]!r} err {err[i]:.3e} bound {bound[i]:.3e}")
+
+
+def fp8_floor(A, B, C, D, r, prec):
+    """Absolute term of the FP8 bound from subnormal rounding:
+    sum_k (da_k |b_k| + |a_k| db_k) <= FP8_SUB (max|a| sum|b| + sum|a| max|b|)
+    per output, over the projected rows of A and columns of B (x2 split: the
+    residual's scale is at most 2^-4 of the value's)."""
+    Ac = np.abs(oracle.project_a(A, C, r))            # r x M x G
+    Bd = np.abs(oracle.project_b(B, D, r))            # r x G x W
+    amax = Ac.max(axis=(0, 2))[:, None]
+    asum = Ac.sum(axis=(0, 2))[:, None]
+    bmax = Bd.max(axis=(0, 1))[None, :]
+    bsum = Bd.sum(axis=(0, 1))[None, :]
+    f = FP8_SUB * (amax * bsum + asum * bmax)
+    return f * (U["fp8"] if prec == "fp8x2" else 1.0)

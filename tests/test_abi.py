@@ -47,6 +47,13 @@ def test_every_declared_symbol_is_exported(lib):
         assert n in pg._SIGNATURES, f"binding lacks {n}"
 
 
+def test_tile_configs(lib):
+    cfgs = pg.tile_configs("f32")
+    assert len(cfgs) >= 4 and (128, 128) in cfgs
+    assert all(m % 32 == 0 and n % 32 == 0 for m, n in cfgs)
+    assert all(m % 16 == 0 for m, _ in pg.tile_configs("f64"))
+
+
 def test_status_strings(lib):
     for c in (OK, ARG, SHAPE, UNSUP, WS, SING, HIP):
         assert pg.status_str(c) and pg.status_str(c) != "unknown status"
@@ -103,6 +110,9 @@ def test_packed_bytes_and_workspace(lib):
     # split modes store two planes
     assert pg.packed_bytes(64, 256, 16, 4, "bf16x3") == 2 * pg.packed_bytes(64, 256, 16, 4, "bf16")
     assert pg.packed_bytes(0, 10, 4, 1) == 0 and pg.packed_bytes(4, 10, 4, 5) == 0
+    # fp8: 2 KiB tiles of 32 rows x 64 indices plus 64 scale bytes per tile
+    assert pg.packed_bytes(32, 64 * 16, 16, 2, "fp8") == 2 * (2048 + 64)
+    assert pg.packed_bytes(32, 64 * 16, 16, 2, "fp8x2") == 2 * pg.packed_bytes(32, 64 * 16, 16, 2, "fp8")
     ws = pg.gemm_workspace_bytes(100, 200, 300, 16, 4, "f32")
     assert ws >= pg.packed_bytes(100, 300, 16, 4) + pg.packed_bytes(200, 300, 16, 4)
     assert pg.gemm_workspace_bytes(100, 200, 300, 16, 17, "f32") == 0
@@ -153,8 +163,33 @@ def test_pack_and_packed_gemm_validation(lib, basis16):
     assert lib.pj_pack_b(b.handle, 4, b"N", 8, 32, FAKE, 7, 1, FAKE, n, None) == SHAPE
     assert lib.pj_pack_b(b.handle, 4, b"T", 8, 32, FAKE, 31, 1, FAKE, n, None) == SHAPE
     assert lib.pj_pack_b(b.handle, 4, b"Q", 8, 32, FAKE, 32, 1, FAKE, n, None) == ARG
-    assert lib.pj_gemm_packed(5, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 8, n, 0.0, FAKE, 8, None) == ARG
-    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 4, n, 0.0, FAKE, 7, None) == SHAPE
-    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, None, 4, n, FAKE, 4, n, 0.0, FAKE, 8, None) == ARG
-    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n - 1, FAKE, 4, n, 0.0, FAKE, 8, None) == WS
-    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 8, n, 0.0, FAKE, 8, None) == WS
+    assert lib.pj_gemm_packed(5, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 8, n, 0.0, FAKE, 8, -1, None) == ARG
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 4, n, 0.0, FAKE, 7, -1, None) == SHAPE
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, None, 4, n, FAKE, 4, n, 0.0, FAKE, 8, -1, None) == ARG
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n - 1, FAKE, 4, n, 0.0, FAKE, 8, -1, None) == WS
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 8, n, 0.0, FAKE, 8, -1, None) == WS
+    assert lib.pj_gemm_packed(4, 8, 8, 32, 16, 1, FAKE, 4, n, FAKE, 4, n, 0.0, FAKE, 8, 99, None) == ARG
+    assert lib.pj_pack_ab(b.handle, 4, b"N", b"X", 8, 8, 32, FAKE, 32, FAKE, 32, 1, FAKE, n, FAKE, n, None) == ARG
+    assert lib.pj_pack_ab(b.handle, 4, b"N", b"T", 8, 8, 32, FAKE, 32, FAKE, 32, 1, FAKE, n, FAKE, n - 1, None) == WS
+
+
+def test_batched_validation(lib, basis16):
+    import ctypes as ct
+    b = basis16
+    D = pg.GemmDesc
+    good = D(8, 8, 32, b"N", b"N", 0x1000, 32, 0x1000, 8, 0x1000, 8)
+    arr = (D * 2)(good, good)
+    n = pg.gemm_batched_workspace_bytes(arr, 16, 4, "f32")
+    assert n > 0
+    p = ct.cast(arr, ct.c_void_p)
+    assert lib.proj_gemm_batched(b.handle, 4, 2, p, 0.0, 1, -1, FAKE, n - 1, None) == WS
+    assert lib.proj_gemm_batched(b.handle, 17, 2, p, 0.0, 1, -1, FAKE, n, None) == ARG
+    assert lib.proj_gemm_batched(b.handle, 4, 0, p, 0.0, 1, -1, FAKE, n, None) == ARG
+    assert lib.proj_gemm_batched(b.handle, 4, 2, p, 0.0, 1, 99, FAKE, n, None) == ARG
+    assert lib.proj_gemm_batched(b.handle, 9, 2, p, 0.0, 6, -1, FAKE, n, None) == UNSUP
+    bad = (D * 2)(good, D(8, 8, 32, b"N", b"N", 0x1000, 31, 0x1000, 8, 0x1000, 8))
+    assert lib.proj_gemm_batched(b.handle, 4, 2, ct.cast(bad, ct.c_void_p), 0.0, 1, -1, FAKE, n, None) == SHAPE
+    nul = (D * 2)(good, D(8, 8, 32, b"N", b"N", 0, 32, 0x1000, 8, 0x1000, 8))
+    assert lib.proj_gemm_batched(b.handle, 4, 2, ct.cast(nul, ct.c_void_p), 0.0, 1, -1, FAKE, n, None) == ARG
+    # the workspace grows with the batch
+    assert pg.gemm_batched_workspace_bytes((D * 3)(good, good, good), 16, 4, "f32") > n

@@ -13,7 +13,7 @@ from tests import _tol
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-KB = {"f64": 8, "f32": 8, "bf16": 16, "f16": 16, "bf16x3": 16, "f16x3": 16}
+KB = {"f64": 8, "f32": 8, "bf16": 16, "f16": 16, "bf16x3": 16, "f16x3": 16, "fp8": 64, "fp8x2": 64}
 
 
 @pytest.fixture(scope="module")
@@ -50,6 +50,8 @@ def _check(pg, A, B, kind, L, r, prec, transA=False, transB=False, Cc=None):
                                    atol=1e-9 * np.abs(ref).max())
     Gp = -(-(-(-A.shape[1] // L)) // KB[prec]) * KB[prec]
     bound = _tol.gemm_bound(prec, L, r, Gp, _tol.magnitude(A, B, C, D, r))
+    if prec.startswith("fp8"):
+        bound = bound + 4.0 * _tol.fp8_floor(A, B, C, D, r, prec)
     _tol.assert_within(got, ref, bound, f"{kind} L={L} r={r} {prec}")
     return got, ref
 
@@ -88,6 +90,38 @@ def test_fp32_images_transB(pg, images, r):
 def test_reduced_precision_images(pg, images, prec, r):
     A, Bt = images
     _check(pg, A, Bt.T, "dct2", 64, r, prec, transB=True)
+
+
+@pytest.mark.parametrize("prec", ["fp8", "fp8x2"])
+@pytest.mark.parametrize("r", [1, 2, 8])
+def test_fp8_images(pg, images, prec, r):
+    """Block-scaled FP8 (one E8M0 scale per 32 projected values), r <= 8."""
+    A, Bt = images
+    got, ref = _check(pg, A, Bt.T, "dct2", 64, r, prec, transB=True)
+    # the split form is markedly closer than the single FP8 rounding
+    if prec == "fp8x2":
+        assert oracle.rel_fro(got, ref) < 2e-3
+
+
+@pytest.mark.parametrize("prec", ["fp8", "fp8x2"])
+def test_fp8_block_scales_vary(pg, prec):
+    """Neighbouring 32-index blocks with magnitudes 2^-12 .. 2^12 apart: a scale
+    applied to the wrong block breaks the bound by orders of magnitude."""
+    rng = np.random.default_rng(33)
+    L, K = 8, 8 * 64 * 4
+    A = rng.standard_normal((40, K)) * np.exp2(4.0 * ((np.arange(K) // (L * 8)) % 7 - 3))[None, :]
+    B = rng.standard_normal((K, 50)) * np.exp2(-3.0 * ((np.arange(K) // (L * 4)) % 9 - 4))[:, None]
+    for r in (1, 2, 8):
+        _check(pg, A, B, "haar", L, r, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp8", "fp8x2"])
+def test_fp8_ragged(pg, prec):
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((70, 333))
+    B = rng.standard_normal((333, 90))
+    for r in (1, 3, 8):
+        _check(pg, A, B, "dct2", 16, r, prec)
 
 
 # ------------------------------------------------------ ragged and layouts
