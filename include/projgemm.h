@@ -167,6 +167,29 @@ int pj_gemm_packed(int r, int M, int W, int K, int L, int prec,
  * tile_n when both are non-NULL.  Used by the autotuner. */
 int pj_gemm_tile_configs(int prec, int* tile_m, int* tile_n, int max_configs);
 
+/* ---------------------------------------------- projected GEMM, backward */
+
+/* Bytes of workspace proj_gemm_backward needs (0 for invalid arguments). */
+size_t pj_gemm_backward_workspace_bytes(int M, int W, int K, int L, int r, int prec);
+
+/* Gradients of R = A Q_{r,K} B (the forward of proj_gemm) for the upstream
+ * gradient dR (M x W, row stride lddr):
+ *   dA = dR (D_N B)_r^T C_N^T restricted to the first r projections of each
+ *        group: dA_hat = dR B_hat^T is one reduced contraction over W, then
+ *        every projected value is spread back over its group with C;
+ *   dB = D_N^T (A C_N)_r^T dR: dB_hat = A_hat^T dR, one reduced contraction
+ *        over M, then spread back with D.
+ * Both reduced contractions have r * ceil(K / L) projected indices on one
+ * side, so they cost r / L of the exact gradients (paper Sec. III-C counts
+ * applied to the two products of the backward pass).  A_hat and B_hat are
+ * re-projected from A and B.  dA (layout of A, stride ldda) and dB (layout of
+ * B, stride lddb) are overwritten; either may be NULL to skip it.  Arrays are
+ * double for PJ_F64 and float otherwise; the two contractions run in `prec`. */
+int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W, int K,
+                       const void* A, int64_t lda, const void* B, int64_t ldb,
+                       const void* dR, int64_t lddr, void* dA, int64_t ldda, void* dB, int64_t lddb,
+                       int prec, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------- batched projected GEMM */
 
 /* One problem of a batch: R <- A Q_{r,K} B + beta R with proj_gemm's

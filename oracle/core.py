@@ -25,7 +25,7 @@ __all__ = [
     "basis_dct2", "basis_haar", "basis_identity", "basis", "invert",
     "gemm", "xcorr", "conv",
     "project_a", "project_b", "gemm_proj", "gemm_proj_block", "gemm_proj_grad",
-    "gemm_proj_closed", "gemm_proj_brute", "q_matrix", "blockdiag",
+    "gemm_proj_closed", "gemm_proj_brute", "q_matrix", "blockdiag", "gemm_proj_grad_block",
     "project_signal", "project_kernel", "xcorr_proj", "xcorr_proj_at",
     "xcorr_proj_closed", "xcorr_proj_sliding",
     "rel_fro", "snr_db", "work_gemm_plain", "work_gemm_proj",
@@ -245,6 +245,36 @@ def gemm_proj_grad(A, B, C, D, r: int, dR):
     dB = np.empty((K, W))
     _ok(_load().or_gemm_proj_grad(M, K, W, L, r, _p(A), _p(B), _p(C), _p(D), _p(dR), _p(dA), _p(dB)),
         "gemm_proj_grad")
+    return dA, dB
+
+
+def gemm_proj_grad_block(A, B, C, D, r: int, dR, rows_a, cols_a, rows_b, cols_b):
+    """Selected gradient entries of R = A Q_{r,K} B: dA[rows_a][:, cols_a] and
+    dB[rows_b][:, cols_b], from the definitions dA = dR (Q B)^T and
+    dB = (A Q)^T dR with Q = blockdiag(C[:, :r] D[:r, :]) (K zero-extended).
+    Each needed row of Q B / column of A Q is formed from its own group."""
+    A, B, dR = _f64(A), _f64(B), _f64(dR)
+    K = A.shape[1]
+    L = _f64(C).shape[0]
+    Q = q_matrix(C, D, r)
+
+    def group(k):
+        j, t = divmod(int(k), L)
+        idx = np.arange(j * L, j * L + L)
+        return t, idx, idx < K
+
+    dA = np.empty((len(rows_a), len(cols_a)))
+    for b_, k in enumerate(cols_a):
+        t, idx, ok = group(k)
+        qb = Q[t, ok] @ B[idx[ok], :]                    # row k of Q B
+        for a_, i in enumerate(rows_a):
+            dA[a_, b_] = float(np.dot(dR[i, :], qb))
+    dB = np.empty((len(rows_b), len(cols_b)))
+    for a_, k in enumerate(rows_b):
+        t, idx, ok = group(k)
+        aq = A[:, idx[ok]] @ Q[ok, t]                    # column k of A Q
+        for b_, w in enumerate(cols_b):
+            dB[a_, b_] = float(np.dot(aq, dR[:, w]))
     return dA, dB
 
 

@@ -24,6 +24,8 @@ struct pj_basis_s {
     float* DTf = nullptr;            // D^T[t][l] = D[l][t] (B side coefficients)
     double* Cd = nullptr;
     double* DTd = nullptr;
+    float* I4f = nullptr;            // 4 x 4 identity: packs an operand unprojected
+    double* I4d = nullptr;
 };
 
 namespace {
@@ -112,6 +114,8 @@ void free_device(pj_basis b)
     (void)hipFree(b->DTf);
     (void)hipFree(b->Cd);
     (void)hipFree(b->DTd);
+    (void)hipFree(b->I4f);
+    (void)hipFree(b->I4d);
     if (prev >= 0) (void)hipSetDevice(prev);
     b->on_device = false;
 }
@@ -142,6 +146,12 @@ bool upload(pj_basis b)
               hipMemcpy(b->DTf, dtf.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(b->Cd, b->C.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(b->DTd, dtd.data(), n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    const float i4f[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    const double i4d[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    ok = ok && hipMalloc((void**)&b->I4f, sizeof(i4f)) == hipSuccess &&
+         hipMalloc((void**)&b->I4d, sizeof(i4d)) == hipSuccess &&
+         hipMemcpy(b->I4f, i4f, sizeof(i4f), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->I4d, i4d, sizeof(i4d), hipMemcpyHostToDevice) == hipSuccess;
     b->on_device = true;   // so that free_device releases partial allocations
     if (!ok) {
         free_device(b);
@@ -181,7 +191,7 @@ PackArgs pack_args(pj_basis b, int rmax, bool a_side, char trans, int rows, int 
     a.K = K;
     a.L = b->L;
     a.r = rmax;
-    if (prec == PJ_F64) a.coef = a_side ? (const void*)b->Cd : (const void*)b->DTd;
+    if (prec == PJ_F64 || prec == P_PLAIN64) a.coef = a_side ? (const void*)b->Cd : (const void*)b->DTd;
     else a.coef = a_side ? (const void*)b->Cf : (const void*)b->DTf;
     a.out = packed;
     a.geom = pack_geom(rows, K, b->L, rmax, prec);
@@ -530,6 +540,123 @@ int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems
     rc = launch_gemm_grouped(prec, (const GroupedProblem*)(w + bp.probs_off), (const GroupedItem*)(w + bp.items_off),
                              bp.nitems, grid, bp.cfg, st);
     return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
+}
+
+// ---------------------------------------------------------------- backward
+
+namespace {
+
+struct BwdPlan {
+    int64_t Gp, rg, T;
+    size_t ahat, bhat, pk, dahat, dbhat, total;
+    size_t p1, p2, p3, p4;
+};
+
+// Plain projections use the FP32 / FP64 fragment geometry (k-blocks of 8).
+BwdPlan plan_bwd(int M, int W, int K, int L, int r, int prec)
+{
+    BwdPlan p;
+    p.T = (prec == PJ_F64) ? 8 : 4;
+    p.Gp = rup(cdiv(K, L), 8);
+    p.rg = (int64_t)r * p.Gp;
+    p.p1 = align256(pj_packed_bytes(M, W, 4, 4, prec));
+    p.p2 = align256(pj_packed_bytes((int)p.rg, W, 4, 4, prec));
+    p.p3 = align256(pj_packed_bytes((int)p.rg, M, 4, 4, prec));
+    p.p4 = align256(pj_packed_bytes(W, M, 4, 4, prec));
+    size_t off = 0;
+    p.ahat = off; off += align256((size_t)M * p.rg * p.T);
+    p.bhat = off; off += align256((size_t)W * p.rg * p.T);
+    p.pk = off; off += std::max(p.p1 + p.p2, p.p3 + p.p4);
+    p.dahat = off; off += align256((size_t)M * p.rg * p.T);
+    p.dbhat = off; off += align256((size_t)p.rg * W * p.T);
+    p.total = off;
+    return p;
+}
+
+}  // namespace
+
+size_t pj_gemm_backward_workspace_bytes(int M, int W, int K, int L, int r, int prec)
+{
+    if (M < 1 || W < 1 || K < 1 || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
+    return plan_bwd(M, W, K, L, r, prec).total;
+}
+
+int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, const void* dR, int64_t lddr, void* dA, int64_t ldda, void* dB,
+                       int64_t lddb, int prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!b || !A || !B || !dR || (!dA && !dB)) return PJ_ERR_ARG;
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    if (r < 1 || r > b->L) return PJ_ERR_ARG;
+    if ((!is_n(transA) && !is_t(transA)) || (!is_n(transB) && !is_t(transB))) return PJ_ERR_ARG;
+    if (M < 1 || W < 1 || K < 1) return PJ_ERR_SHAPE;
+    if (lda < (is_n(transA) ? (int64_t)K : (int64_t)M)) return PJ_ERR_SHAPE;
+    if (ldb < (is_n(transB) ? (int64_t)W : (int64_t)K)) return PJ_ERR_SHAPE;
+    if (lddr < W) return PJ_ERR_SHAPE;
+    if (dA && ldda < (is_n(transA) ? (int64_t)K : (int64_t)M)) return PJ_ERR_SHAPE;
+    if (dB && lddb < (is_n(transB) ? (int64_t)W : (int64_t)K)) return PJ_ERR_SHAPE;
+    const BwdPlan pl = plan_bwd(M, W, K, b->L, r, prec);
+    if (pl.rg > 0x7fffffff) return PJ_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < pl.total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)ws;
+    const bool f64 = (prec == PJ_F64);
+    const int plain = f64 ? P_PLAIN64 : P_PLAIN32;
+    const void* I4 = f64 ? (const void*)b->I4d : (const void*)b->I4f;
+
+    // 1. plain projections of A (with C) and B (with D^T): M x rG and W x rG
+    PackArgs pa[2] = {pack_args(b, r, true, transA, M, K, A, lda, plain, w + pl.ahat),
+                      pack_args(b, r, false, transB, W, K, B, ldb, plain, w + pl.bhat)};
+    pa[0].geom = pack_geom(M, K, b->L, r, plain);
+    pa[1].geom = pack_geom(W, K, b->L, r, plain);
+    pa[0].plain_ld = pa[1].plain_ld = pl.rg;
+    if (launch_pack_n(plain, pa, 2, st) != 0) return PJ_ERR_HIP;
+
+    // packs an unprojected operand: rows x Kc of src (trans as given) with
+    // the 4 x 4 identity, i.e. the contraction index merely permuted
+    auto unproj = [&](const void* src, int64_t ld, int trans, int64_t rows, int64_t Kc, void* dst) {
+        PackArgs u;
+        u.X = src; u.ld = ld; u.trans = trans; u.P = rows; u.K = Kc; u.L = 4; u.r = 4;
+        u.coef = I4; u.out = dst; u.geom = pack_geom(rows, Kc, 4, 4, prec);
+        return u;
+    };
+    auto gemm = [&](const void* X, int64_t P, const void* Y, int64_t Q, int64_t Kc, void* R, int64_t ldr) {
+        GemmArgs g;
+        g.X = X; g.gx = pack_geom(P, Kc, 4, 4, prec);
+        g.Y = Y; g.gy = pack_geom(Q, Kc, 4, 4, prec);
+        g.nkb = 4 * g.gx.Gp / layout_of(prec).KB;
+        g.P = P; g.Q = Q; g.R = R; g.ldr = ldr; g.beta = 0.0f;
+        return launch_gemm(prec, g, -1, st);
+    };
+    char* p1 = w + pl.pk;
+    if (dA) {
+        // 2. dA_hat = dR B_hat: contraction over the W columns of R
+        PackArgs u[2] = {unproj(dR, lddr, 0, M, W, p1), unproj(w + pl.bhat, pl.rg, 1, pl.rg, W, p1 + pl.p1)};
+        if (launch_pack_n(prec, u, 2, st) != 0) return PJ_ERR_HIP;
+        if (gemm(p1, M, p1 + pl.p1, pl.rg, W, w + pl.dahat, pl.rg) != 0) return PJ_ERR_HIP;
+        // 3. dA = dA_hat spread back over each group with C
+        ExpandArgs e;
+        e.in = w + pl.dahat; e.ldi = pl.rg; e.in_trans = 0;
+        e.out = dA; e.ldo = ldda; e.out_trans = is_t(transA) ? 1 : 0;
+        e.P = M; e.K = K; e.L = b->L; e.r = r; e.Gp = pl.Gp;
+        e.coef = f64 ? (const void*)b->Cd : (const void*)b->Cf;
+        if (launch_expand(f64, e, st) != 0) return PJ_ERR_HIP;
+    }
+    if (dB) {
+        // 4. dB_hat = A_hat^T dR: contraction over the M rows of R
+        PackArgs u[2] = {unproj(w + pl.ahat, pl.rg, 1, pl.rg, M, p1), unproj(dR, lddr, 1, W, M, p1 + pl.p3)};
+        if (launch_pack_n(prec, u, 2, st) != 0) return PJ_ERR_HIP;
+        if (gemm(p1, pl.rg, p1 + pl.p3, W, M, w + pl.dbhat, W) != 0) return PJ_ERR_HIP;
+        // 5. dB = dB_hat spread back over each group with D
+        ExpandArgs e;
+        e.in = w + pl.dbhat; e.ldi = W; e.in_trans = 1;
+        e.out = dB; e.ldo = lddb; e.out_trans = is_n(transB) ? 1 : 0;
+        e.P = W; e.K = K; e.L = b->L; e.r = r; e.Gp = pl.Gp;
+        e.coef = f64 ? (const void*)b->DTd : (const void*)b->DTf;
+        if (launch_expand(f64, e, st) != 0) return PJ_ERR_HIP;
+    }
+    return PJ_OK;
 }
 
 size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec)

@@ -9,7 +9,10 @@
 
 namespace pj {
 
-enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_F16 = 4, P_F16X3 = 5, P_FP8 = 6, P_FP8X2 = 7 };
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_F16 = 4, P_F16X3 = 5, P_FP8 = 6, P_FP8X2 = 7,
+            // internal: projections written as a plain row-major matrix
+            // (rows x r*Gp, element (p, l*Gp + j)) in FP32 or FP64
+            P_PLAIN32 = 8, P_PLAIN64 = 9 };
 
 // ---------------------------------------------------------------------------
 // Packed ("fragment-order") operand layout.
@@ -56,6 +59,8 @@ __host__ __device__ constexpr Layout layout_of(int prec)
     case P_F16X3: return Layout{2, 32, 2, 8, 16, 16, 2, 0};
     case P_FP8:   return Layout{1, 32, 2, 32, 64, 32, 1, 1};
     case P_FP8X2: return Layout{1, 32, 2, 32, 64, 32, 2, 1};
+    case P_PLAIN32: return Layout{4, 32, 2, 4, 8, 16, 1, 0};
+    case P_PLAIN64: return Layout{8, 16, 4, 2, 8, 16, 1, 0};
     default:      return Layout{0, 0, 0, 0, 0, 0, 0, 0};
     }
 }
@@ -112,6 +117,7 @@ struct PackArgs {
                        // source index t in projection l (float or double)
     void* out;         // packed operand
     PackGeom geom;
+    int64_t plain_ld = 0;  // row stride of a plain output (P_PLAIN32 / P_PLAIN64)
 };
 int launch_pack(int prec, const PackArgs& a, hipStream_t s);
 // Packs n (1 or 2) operands of the same precision in one launch.
@@ -129,6 +135,18 @@ struct GemmArgs {
     void* R; int64_t ldr;        // P x Q row-major, float (double for F64)
     float beta;
 };
+// Synthesis with the projection coefficients (the transpose of the pack's
+// projection): out(p, jL + t) = sum_{l<r} in(p, l*Gp + j) coef[t, l].
+struct ExpandArgs {
+    const void* in; int64_t ldi; int in_trans;     // in(p, kk) at in[p*ldi+kk] or in[kk*ldi+p]
+    void* out; int64_t ldo; int out_trans;         // out(p, k) at out[p*ldo+k] or out[k*ldo+p]
+    int64_t P, K;
+    int L, r;
+    int64_t Gp;
+    const void* coef;                              // L x L, element (t, l)
+};
+int launch_expand(int is_double, const ExpandArgs& a, hipStream_t s);
+
 // One problem of a grouped launch, as stored in device memory.
 struct GroupedProblem {
     const void* X; int64_t x_nrb, x_nkb, x_plane, x_pb;

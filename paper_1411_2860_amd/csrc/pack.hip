@@ -41,7 +41,7 @@ struct PackJob {
     int L, r;
     const TIn* coef; // L x L, element (t, l)
     char* out;
-    int64_t nkb, Gp, plane_stride, plane_bytes;
+    int64_t nkb, Gp, plane_stride, plane_bytes, plain_ld;
     int64_t nrb, ngt;   // row blocks, group tiles (Gp / KB)
     int TC, TCp, JS, RS;
 };
@@ -275,7 +275,14 @@ __device__ inline void pack_tile(const PackJob<TIn>& J, int64_t tix)
 #pragma unroll
             for (int q = 0; q < RL; ++q) {
                 const int l = lb + q;
-                if (l < r) {
+                if constexpr (PREC == P_PLAIN32 || PREC == P_PLAIN64) {
+                    const int64_t p = p0 + row;
+                    if (l < r && p < J.P) {
+                        TIn* dst = reinterpret_cast<TIn*>(J.out) + p * J.plain_ld + (int64_t)l * J.Gp + j0 + g * E;
+#pragma unroll
+                        for (int e = 0; e < E; ++e) dst[e] = acc[c][q][e];
+                    }
+                } else if (l < r) {
                     const int64_t kbi = ((int64_t)l * J.Gp + j0) / KB;
                     const int64_t off = ((rbi * J.nkb + kbi) * 64 + lane) * ly.LB;
                     store_lane<PREC, E, TIn>(J.out, off, J.plane_stride, J.plane_bytes, acc[c][q]);
@@ -330,6 +337,7 @@ PackJob<TIn> make_job(const PackArgs& a)
     j.Gp = g.Gp;
     j.plane_stride = g.plane_bytes + g.scale_plane;
     j.plane_bytes = g.plane_bytes;
+    j.plain_ld = a.plain_ld;
     j.nrb = g.nrb;
     j.ngt = g.Gp / ly.KB;
     // chunk of t staged per round: the largest divisor of L whose padded tile
@@ -431,6 +439,8 @@ int launch_pack_n(int prec, const PackArgs* a, int n, hipStream_t s)
     case P_F16X3:  return launch_p<float, P_F16X3>(a, n, s);
     case P_FP8:    return launch_p<float, P_FP8>(a, n, s);
     case P_FP8X2:  return launch_p<float, P_FP8X2>(a, n, s);
+    case P_PLAIN32: return launch_p<float, P_PLAIN32>(a, n, s);
+    case P_PLAIN64: return launch_p<double, P_PLAIN64>(a, n, s);
     default:       return -2;
     }
 }

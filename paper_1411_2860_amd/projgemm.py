@@ -16,7 +16,7 @@ import numpy as np
 __all__ = [
     "ProjGemmError", "lib", "lib_path", "Basis", "PREC", "BASIS",
     "gemm", "pack_a", "pack_b", "pack_ab", "tile_configs", "gemm_packed", "packed_bytes", "gemm_workspace_bytes",
-    "conv1d", "conv1d_workspace_bytes", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
+    "conv1d", "conv1d_workspace_bytes", "gemm_backward", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
     "status_str",
 ]
 
@@ -66,6 +66,9 @@ _SIGNATURES = {
     "pj_conv1d_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i]),
     "pj_gemm_batched_workspace_bytes": (_sz, [_i, _vp, _i, _i, _i, _i]),
     "proj_gemm_batched": (_i, [_vp, _i, _i, _vp, _f, _i, _i, _vp, _sz, _vp]),
+    "pj_gemm_backward_workspace_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
+    "proj_gemm_backward": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                _i64, _i, _vp, _sz, _vp]),
     "proj_conv1d": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
 }
 
@@ -335,3 +338,25 @@ def gemm_batched(As, Bs, r: int, basis: Basis, prec="bf16", transA=False, transB
                                    int(tile_cfg), _ptr(workspace), workspace.numel(), _stream(stream)),
            "proj_gemm_batched")
     return outs
+
+
+def gemm_backward(A, B, dR, r: int, basis: Basis, prec="f32", transA=False, transB=False, need_dA=True,
+                  need_dB=True, workspace=None, stream=None):
+    """(dA, dB) of R = A Q_{r,K} B for upstream dR; dA has A's layout, dB B's."""
+    import torch
+    p = _prec(prec)
+    M, K = (A.shape[1], A.shape[0]) if transA else tuple(A.shape)
+    W = B.shape[0] if transB else B.shape[1]
+    dA = torch.empty_like(A) if need_dA else None
+    dB = torch.empty_like(B) if need_dB else None
+    if dR.stride(1) != 1:
+        dR = dR.contiguous()
+    need = int(lib().pj_gemm_backward_workspace_bytes(M, W, K, basis.L, r, p))
+    if workspace is None:
+        workspace = _byte_buffer(need, A.device)
+    _check(lib().proj_gemm_backward(basis.handle, r, b"T" if transA else b"N", b"T" if transB else b"N", M, W, K,
+                                    _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(dR), dR.stride(0),
+                                    _ptr(dA) if dA is not None else None, dA.stride(0) if dA is not None else 1,
+                                    _ptr(dB) if dB is not None else None, dB.stride(0) if dB is not None else 1,
+                                    p, _ptr(workspace), workspace.numel(), _stream(stream)), "proj_gemm_backward")
+    return dA, dB

@@ -275,3 +275,16 @@ def test_gradient_full_r_is_exact_gradient():
     dA, dB = oracle.gemm_proj_grad(A, B, C, D, L, dR)
     np.testing.assert_allclose(dA, dR @ B.T, rtol=1e-11, atol=1e-11)
     np.testing.assert_allclose(dB, A.T @ dR, rtol=1e-11, atol=1e-11)
+
+
+def test_gradient_block_matches_full():
+    L = 8
+    C, D = oracle.basis("dct2", L)
+    A, B = _rand((6, 21), 40), _rand((21, 5), 41)
+    dR = _rand((6, 5), 42)
+    for r in (1, 3, 8):
+        dA, dB = oracle.gemm_proj_grad(A, B, C, D, r, dR)
+        ra, ca, rb, cb = [0, 5], [0, 7, 20], [3, 16, 20], [1, 4]
+        dAb, dBb = oracle.gemm_proj_grad_block(A, B, C, D, r, dR, ra, ca, rb, cb)
+        np.testing.assert_allclose(dAb, dA[np.ix_(ra, ca)], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(dBb, dB[np.ix_(rb, cb)], rtol=1e-12, atol=1e-12)
