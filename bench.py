@@ -1,16 +1,19 @@
 #!/usr/bin/env python3
-"""Benchmark of the projected GEMM on one MI355X.
+"""Benchmark of the projected GEMM / cross-correlation on one MI355X.
 
-Workload (recognition-shaped projected GEMM): 1024 query images x 8192
-database images, each a 64 x 64 Gaussian-smoothed noise image with values
+Headline workload (recognition-shaped projected GEMM): 1024 query images x
+8192 database images, each a 64 x 64 Gaussian-smoothed noise image with values
 0..255 (K = 4096); the database is stored as 8192 rows of 4096 (B^T).  L = 64
-DCT-II, FP32 operands and accumulation.  One step = the whole hot path on
-inputs already resident in HBM: project-and-pack A, project-and-pack B, the
-reduced MFMA contraction over r * K / L projected indices (paper Sec. III-B).
+DCT-II, FP32 operands and accumulation, r = 16.  One step = the whole hot path
+on inputs already resident in HBM: one launch that projects and packs A and B,
+then the reduced MFMA contraction over r * K / L projected indices (paper
+Sec. III-B), with the tile chosen by the autotuner.
 
 Prints ONE JSON line.  `value` is exact-equivalent TFLOP/s (2 M K W flops per
-step, whatever r) at the headline r; `per_r` holds the sweep with the error
-against FP64 (exact product and projected oracle) on sampled outputs.
+step, whatever r).  Extra sections: the r sweep with errors against FP64 (exact
+product and projected oracle) on sampled outputs, the precision ladder, the
+plain FP32 GEMM through the same kernels, the 2^22-sample projected
+cross-correlation, the 64-problem batch, and the MLP forward + backward.
 """
 from __future__ import annotations
 
@@ -19,19 +22,28 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+os.environ.setdefault("PROJGEMM_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "projgemm_tune_bench.json"))
 
 M, K, W, L = 1024, 4096, 8192, 64
 HEADLINE_R = 16
 SWEEP = [1, 2, 4, 8, 12, 16, 24, 32, 48, 64]
-PEAK_FP32_MFMA = 157.3    # TFLOP/s, MI355X dense FP32 matrix
-PEAK_HBM = 8000.0         # GB/s
+PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500.0, "f16x3": 2500.0,
+        "fp8": 5000.0, "fp8x2": 5000.0}      # dense MFMA TFLOP/s of the operand format
+MFMA_PER_PRODUCT = {"bf16x3": 3, "f16x3": 3, "fp8x2": 3}
+PEAK_HBM = 8000.0                            # GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f32_recognition_traffic.json")
+SECTIONS = ["sweep", "precisions", "plain", "conv", "batched", "mlp"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sources_hash() -> str:
@@ -42,13 +54,6 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_inputs():
-    from paper_1411_2860_amd import inputs
-    A = inputs.image_rows(M, seed_base=inputs.SEED_IMG_BASE)
-    Bt = inputs.image_rows(W, seed_base=inputs.SEED_IMG_BASE, first=M)
-    return A, Bt
-
-
 def cpu_baseline(A, Bt, r):
     """The FP64 oracle on a bounded sample: the first `rows` query rows against
     all 8192 database columns (the B projection is included in full), sized
@@ -57,6 +62,7 @@ def cpu_baseline(A, Bt, r):
     C, D = oracle.basis("dct2", L)
     cols = np.arange(W)
     Bk = np.ascontiguousarray(Bt.T)
+
     def run(n):
         t0 = time.perf_counter()
         oracle.gemm_proj_block(A, Bk, C, D, r, np.arange(n), cols)
@@ -65,13 +71,15 @@ def cpu_baseline(A, Bt, r):
     per_row = max((t40 - t8) / 32.0, 1e-4)
     rows = int((15.0 - t8) / per_row) if t8 < 15.0 else 8
     rows = min(M, max(8, rows // 8 * 8))
-    t0 = time.perf_counter()
-    oracle.gemm_proj_block(A, Bk, C, D, r, np.arange(rows), cols)
-    t = time.perf_counter() - t0
-    return {"value": 2.0 * rows * K * W / t / 1e12, "unit": "exact-equivalent TFLOP/s",
+    t = run(rows)
+    return {"value": round(2.0 * rows * K * W / t / 1e12, 6), "unit": "exact-equivalent TFLOP/s",
             "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{rows} of {M} query rows x all {W} database columns, r={r}, L={L}, "
                       f"FP64 pipeline (project A, project B, accumulate); {t:.1f} s"}
+
+
+def f3(x):
+    return float(f"{x:.3e}")
 
 
 def main():
@@ -80,25 +88,33 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--r", type=int, default=HEADLINE_R)
-    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sections", default=",".join(SECTIONS),
+                    help="comma list of extra sections (" + ",".join(SECTIONS) + ") or 'none'")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
-                    help="few steps, no sweep, no CPU leg, plus a plain copy of known size (for counter scaling)")
+                    help="headline only, few steps, no CPU leg, plus a plain copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the projected GEMM path is single-GPU in this build "
-              "(sharding is described in the design notes, not implemented)", file=sys.stderr)
+              "(sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_1411_2860_amd import projgemm as pg
+    from paper_1411_2860_amd import autotune, inputs, projgemm as pg
 
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     pg.lib()
     dev = torch.device("cuda:0")
-    A, Bt = make_inputs()
+    sections = [] if args.sections == "none" else [s for s in args.sections.split(",") if s]
+    if args.profile:
+        sections, args.no_cpu = [], True
+        args.steps, args.warmup = min(args.steps, 5), min(args.warmup, 2)
+
+    log("generating inputs")
+    A = inputs.image_rows(M, seed_base=inputs.SEED_IMG_BASE)
+    Bt = inputs.image_rows(W, seed_base=inputs.SEED_IMG_BASE, first=M)
     Ad = torch.from_numpy(A.astype(np.float32)).to(dev)
     Bd = torch.from_numpy(Bt.astype(np.float32)).to(dev)
     basis = pg.Basis("dct2", L)
@@ -110,52 +126,50 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        args.steps, args.warmup, args.no_sweep, args.no_cpu = min(args.steps, 5), min(args.warmup, 2), True, True
 
-    def setup(r):
-        Ap = torch.empty(pg.packed_bytes(M, K, L, r), dtype=torch.uint8, device=dev)
-        Bp = torch.empty(pg.packed_bytes(W, K, L, r), dtype=torch.uint8, device=dev)
+    def timed(r, prec, steps, warmup, b=basis, Lb=L):
+        cfg = autotune.tune_gemm(M, W, K, Lb, r, prec, reps=3, basis=b)
+        Ap = torch.empty(pg.packed_bytes(M, K, Lb, r, prec), dtype=torch.uint8, device=dev)
+        Bp = torch.empty(pg.packed_bytes(W, K, Lb, r, prec), dtype=torch.uint8, device=dev)
         R = torch.empty((M, W), dtype=torch.float32, device=dev)
-        return Ap, Bp, R
 
-    def step(r, bufs, ev=None):
-        Ap, Bp, R = bufs
-        pg.pack_a(Ad, r, basis, out=Ap)
-        pg.pack_b(Bd, r, basis, transB=True, out=Bp)
-        if ev is not None:
-            ev[0].record()
-        pg.gemm_packed(Ap, Bp, r, M, W, K, L, r, r, out=R)
-        if ev is not None:
-            ev[1].record()
-
-    def timed(r, steps, warmup, kernel_events=False):
-        bufs = setup(r)
+        def step(ev=None):
+            pg.pack_ab(Ad, Bd, r, b, prec=prec, transB=True, out_a=Ap, out_b=Bp)
+            if ev is not None:
+                ev[0].record()
+            pg.gemm_packed(Ap, Bp, r, M, W, K, Lb, r, r, prec=prec, out=R, tile_cfg=cfg)
+            if ev is not None:
+                ev[1].record()
         for _ in range(warmup):
-            step(r, bufs)
+            step()
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(steps)] if kernel_events else [None] * steps
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t0 = time.perf_counter()
         for i in range(steps):
-            step(r, bufs, evs[i])
+            step(evs[i])
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
-        kms = float(np.mean([a.elapsed_time(b) for a, b in evs])) if kernel_events else None
-        return ms, kms, bufs
+        kms = float(np.mean([a.elapsed_time(e) for a, e in evs]))
+        return ms, kms, R, cfg
+
+    rng_s = np.random.default_rng(1234)
+    srows = np.sort(rng_s.choice(M, 64, replace=False))
+    scols = np.sort(rng_s.choice(W, 64, replace=False))
+    exact_block = A[srows] @ Bt[scols].T
+    proj_cache = {}
 
     def sampled_errors(r, R):
-        rng = np.random.default_rng(1234)
-        rows = np.sort(rng.choice(M, 64, replace=False))
-        cols = np.sort(rng.choice(W, 64, replace=False))
-        got = R[torch.from_numpy(rows).to(dev)][:, torch.from_numpy(cols).to(dev)].double().cpu().numpy()
         import oracle
-        proj = oracle.gemm_proj_block(A, np.ascontiguousarray(Bt.T), C, D, r, rows, cols)
-        exact = A[rows] @ Bt[cols].T
-        return oracle.rel_fro(got, exact), oracle.rel_fro(got, proj), oracle.rel_fro(proj, exact)
+        got = R[torch.from_numpy(srows).to(dev)][:, torch.from_numpy(scols).to(dev)].double().cpu().numpy()
+        if r not in proj_cache:
+            proj_cache[r] = oracle.gemm_proj_block(A, np.ascontiguousarray(Bt.T), C, D, r, srows, scols)
+        proj = proj_cache[r]
+        return oracle.rel_fro(got, exact_block), oracle.rel_fro(got, proj), oracle.rel_fro(proj, exact_block)
 
-    r = args.r
-    ms, kms, bufs = timed(r, args.steps, args.warmup, kernel_events=True)
     exact_flops = 2.0 * M * K * W
+    r = args.r
+    log(f"headline r={r}")
+    ms, kms, R, cfg = timed(r, "f32", args.steps, args.warmup)
     value = exact_flops / (ms * 1e-3) / 1e12
     gemm_flops = 2.0 * M * W * r * (K // L)
     achieved = gemm_flops / (kms * 1e-3) / 1e12
@@ -177,54 +191,189 @@ def main():
         "dtype": "f32", "data": "synthetic (seeded smoothed 64x64 images, 0..255)",
         "config": {"workload": f"recognition-shaped projected GEMM: {M} queries x {W} database images "
                                f"of 64x64 (K={K}), database stored {W}x{K}, L={L} DCT-II, r={r}, FP32",
-                   "M": M, "K": K, "W": W, "L": L, "r": r, "basis": "dct2", "prec": "f32",
+                   "M": M, "K": K, "W": W, "L": L, "r": r, "basis": "dct2", "prec": "f32", "tile_cfg": cfg,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": traffic,
-                     "kernel": "gemm_kernel<F32> (reduced contraction)",
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f32"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4), "traffic": traffic,
+                     "kernel": "gemm_kernel (reduced contraction, FP32)",
                      "kernel_ms": round(kms, 5), "algorithmic_flops_per_launch": gemm_flops},
     }
+    e_exact, e_proj, _ = sampled_errors(r, R)
+    out["rel_err_vs_fp64_exact"] = f3(e_exact)
+    out["rel_err_vs_fp64_projected"] = f3(e_proj)
+    del R
 
-    if not args.no_sweep:
-        per_r = []
+    def section(name, fn):
+        if name not in sections:
+            return
+        log(f"section {name}")
+        t0 = time.perf_counter()
+        try:
+            out[name] = fn()
+        except Exception as ex:   # a failing section is reported, the headline still prints
+            out[name] = {"error": f"{type(ex).__name__}: {ex}"}
+        log(f"section {name} done in {time.perf_counter() - t0:.1f} s")
+
+    def sec_sweep():
+        res = []
         for rr in SWEEP:
-            ms_r, kms_r, bufs_r = timed(rr, 10, 3, kernel_events=True)
-            e_exact, e_proj, e_method = sampled_errors(rr, bufs_r[2])
-            per_r.append({"r": rr, "ms_per_step": round(ms_r, 5), "gemm_ms": round(kms_r, 5),
-                          "exact_equiv_tflops": round(exact_flops / (ms_r * 1e-3) / 1e12, 3),
-                          "rel_err_vs_fp64_exact": float(f"{e_exact:.3e}"),
-                          "rel_err_vs_fp64_projected": float(f"{e_proj:.3e}"),
-                          "method_rel_err": float(f"{e_method:.3e}")})
-            del bufs_r
-        out["per_r"] = per_r
+            ms_r, kms_r, R_r, cfg_r = timed(rr, "f32", 10, 3)
+            e1, e2, e3 = sampled_errors(rr, R_r)
+            res.append({"r": rr, "ms_per_step": round(ms_r, 5), "gemm_ms": round(kms_r, 5), "tile_cfg": cfg_r,
+                        "exact_equiv_tflops": round(exact_flops / (ms_r * 1e-3) / 1e12, 3),
+                        "gemm_frac_of_fp32_peak": round(2.0 * M * W * rr * (K // L) / (kms_r * 1e-3) / 1e12
+                                                        / PEAK["f32"], 4),
+                        "rel_err_vs_fp64_exact": f3(e1), "rel_err_vs_fp64_projected": f3(e2),
+                        "method_rel_err": f3(e3)})
+            del R_r
+        return res
+
+    def sec_precisions():
+        res = []
+        for prec, rr in [("bf16x3", r), ("f16x3", r), ("bf16", r), ("f16", r), ("bf16x3", 64), ("bf16", 64),
+                         ("fp8", 8), ("fp8x2", 8), ("fp8", 1)]:
+            ms_p, kms_p, R_p, cfg_p = timed(rr, prec, 10, 3)
+            e1, e2, _ = sampled_errors(rr, R_p)
+            mfma_flops = 2.0 * M * W * rr * (K // L) * MFMA_PER_PRODUCT.get(prec, 1)
+            res.append({"prec": prec, "r": rr, "ms_per_step": round(ms_p, 5), "gemm_ms": round(kms_p, 5),
+                        "tile_cfg": cfg_p, "exact_equiv_tflops": round(exact_flops / (ms_p * 1e-3) / 1e12, 3),
+                        "gemm_frac_of_peak": round(mfma_flops / (kms_p * 1e-3) / 1e12 / PEAK[prec], 4),
+                        "rel_err_vs_fp64_exact": f3(e1), "rel_err_vs_fp64_projected": f3(e2)})
+            del R_p
+        return res
+
+    def sec_plain():
         # plain (unprojected) FP32 GEMM through the same kernels: the identity
         # basis with all projections kept only permutes the contraction index
-        PL = 4
-        plain = pg.Basis("identity", PL)
-        Ap = torch.empty(pg.packed_bytes(M, K, PL, PL), dtype=torch.uint8, device=dev)
-        Bp = torch.empty(pg.packed_bytes(W, K, PL, PL), dtype=torch.uint8, device=dev)
-        Rp = torch.empty((M, W), dtype=torch.float32, device=dev)
+        plain = pg.Basis("identity", 4)
+        ms_p, kms_p, R_p, cfg_p = timed(4, "f32", 10, 3, b=plain, Lb=4)
+        import oracle
+        got = R_p[torch.from_numpy(srows).to(dev)][:, torch.from_numpy(scols).to(dev)].double().cpu().numpy()
+        return {"ms_per_step": round(ms_p, 5), "gemm_ms": round(kms_p, 5), "tile_cfg": cfg_p,
+                "tflops": round(exact_flops / (ms_p * 1e-3) / 1e12, 3),
+                "gemm_frac_of_fp32_peak": round(exact_flops / (kms_p * 1e-3) / 1e12 / PEAK["f32"], 4),
+                "rel_err_vs_fp64_exact": f3(oracle.rel_fro(got, exact_block)),
+                "speedup_of_headline_r": round(ms_p / ms, 3)}
 
-        def pstep():
-            pg.pack_a(Ad, PL, plain, out=Ap)
-            pg.pack_b(Bd, PL, plain, transB=True, out=Bp)
-            pg.gemm_packed(Ap, Bp, PL, M, W, K, PL, PL, PL, out=Rp)
-        for _ in range(3):
-            pstep()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            pstep()
-        torch.cuda.synchronize()
-        pms = (time.perf_counter() - t0) * 1e3 / 5
-        out["plain_fp32_gemm"] = {"ms_per_step": round(pms, 5),
-                                  "tflops": round(exact_flops / (pms * 1e-3) / 1e12, 3),
-                                  "speedup_of_headline_r": round(pms / ms, 3)}
-        e_exact, e_proj, _ = sampled_errors(r, bufs[2])
-        out["rel_err_vs_fp64_exact"] = float(f"{e_exact:.3e}")
-        out["rel_err_vs_fp64_projected"] = float(f"{e_proj:.3e}")
+    def sec_conv():
+        import oracle
+        Wc, Lc = 1 << 22, 256
+        s = inputs.ar2_signal(Wc, seed=inputs.SEED_AR2)
+        sd = torch.from_numpy(s.astype(np.float32)).to(dev)
+        bc = pg.Basis("dct2", Lc)
+        Cc, Dc = bc.matrices()
+        ident = pg.Basis("identity", 32)
+        res = []
+        for N in (1024, 4096, 16384):
+            k, o = inputs.excerpt_kernel(s, N, seed=inputs.SEED_KERNEL)
+            kd = torch.from_numpy(k.astype(np.float32)).to(dev)
+            nout = Wc - N + 1
+            y = torch.empty(nout, dtype=torch.float32, device=dev)
+            ms_rng = np.random.default_rng(N)
+            ms = np.unique(np.concatenate([[0, nout - 1, o], ms_rng.integers(0, nout, 61)]))
+            exact = np.array([np.dot(k, s[m:m + N]) for m in ms])
+            flops = 2.0 * nout * N
+            for rr, b, lab in [(1, bc, "dct2"), (16, bc, "dct2"), (64, bc, "dct2"), (256, bc, "dct2"),
+                               (32, ident, "plain")]:
+                ws = torch.empty(pg.conv1d_workspace_bytes(Wc, N, b.L, rr), dtype=torch.uint8, device=dev)
+                fn = lambda: pg.conv1d(sd, kd, rr, b, out=y, workspace=ws)
+                t = autotune._time_ms(fn, 10, warmup=3)
+                got = y[torch.from_numpy(ms).to(dev)].double().cpu().numpy()
+                ent = {"N": N, "basis": lab, "L": b.L, "r": rr, "ms": round(t, 5),
+                       "exact_equiv_tflops": round(flops / (t * 1e-3) / 1e12, 3),
+                       "rel_err_vs_fp64_exact": f3(oracle.rel_fro(got, exact))}
+                if lab == "dct2":
+                    proj = oracle.xcorr_proj_at(s, k, Cc, Dc, rr, ms)
+                    ent["rel_err_vs_fp64_projected"] = f3(oracle.rel_fro(got, proj))
+                res.append(ent)
+                del ws
+        return res
+
+    def sec_batched():
+        import oracle
+        shapes = inputs.batched_shapes()
+        As, Bs = [], []
+        for i, (m, w, k) in enumerate(shapes):
+            As.append(torch.from_numpy(inputs.smoothed_rows(m, k, sigma=4.0, seed=6400 + i).astype(np.float32)).to(dev))
+            Bs.append(torch.from_numpy(inputs.gaussian_matrix(k, w, seed=64000 + i).astype(np.float32)).to(dev))
+        flops = sum(2.0 * m * w * k for m, w, k in shapes)
+        Lb = 16
+        bb = pg.Basis("dct2", Lb)
+        Cb, Db = bb.matrices()
+        res = []
+        for prec, rr in [("bf16x3", 4), ("bf16", 4), ("bf16", 16), ("fp8", 8), ("f16x3", 16)]:
+            cfg_b = autotune.tune_batched(As, Bs, rr, bb, prec=prec, reps=2, candidates=[0, 2, 4, 6])
+            outs = pg.gemm_batched(As, Bs, rr, bb, prec=prec, tile_cfg=cfg_b)
+            descs = pg._descs(As, Bs, outs)
+            ws = torch.empty(pg.gemm_batched_workspace_bytes(descs, Lb, rr, prec, cfg_b), dtype=torch.uint8,
+                             device=dev)
+            t = autotune._time_ms(lambda: pg.gemm_batched(As, Bs, rr, bb, prec=prec, outs=outs, tile_cfg=cfg_b,
+                                                           workspace=ws), 5, warmup=2)
+            errs = []
+            rng = np.random.default_rng(rr)
+            for i in range(0, len(shapes), 8):      # every 8th problem, 8 x 8 samples
+                m, w, k = shapes[i]
+                rows = np.sort(rng.choice(m, 8, replace=False))
+                cols = np.sort(rng.choice(w, 8, replace=False))
+                got = outs[i][torch.from_numpy(rows).to(dev)][:, torch.from_numpy(cols).to(dev)].double().cpu().numpy()
+                A64 = As[i].double().cpu().numpy()
+                B64 = Bs[i].double().cpu().numpy()
+                proj = oracle.gemm_proj_block(A64, B64, Cb, Db, rr, rows, cols)
+                errs.append((oracle.rel_fro(got, proj), oracle.rel_fro(got, A64[rows] @ B64[:, cols])))
+            res.append({"prec": prec, "r": rr, "L": Lb, "problems": len(shapes), "tile_cfg": cfg_b,
+                        "ms": round(t, 4), "exact_equiv_tflops": round(flops / (t * 1e-3) / 1e12, 3),
+                        "reduced_tflops": round(flops * rr / Lb / (t * 1e-3) / 1e12, 3),
+                        "rel_err_vs_fp64_projected_max": f3(max(e[0] for e in errs)),
+                        "rel_err_vs_fp64_exact_max": f3(max(e[1] for e in errs))})
+            del ws, outs
+        return res
+
+    def sec_mlp():
+        from paper_1411_2860_amd.autograd import proj_matmul
+        import oracle
+        Bsz, Din, Dh, Dout = 4096, 4096, 4096, 1024
+        X = (inputs.image_rows(Bsz, seed_base=8000) / 255.0)
+        W1 = inputs.gaussian_matrix(Din, Dh, seed=5, scale=1 / 64.0)
+        W2 = inputs.gaussian_matrix(Dh, Dout, seed=6, scale=1 / 64.0)
+        T = inputs.gaussian_matrix(Bsz, Dout, seed=8)
+        Xd = torch.from_numpy(X.astype(np.float32)).to(dev)
+        Td = torch.from_numpy(T.astype(np.float32)).to(dev)
+        W1d = torch.from_numpy(W1.astype(np.float32)).to(dev).requires_grad_()
+        W2d = torch.from_numpy(W2.astype(np.float32)).to(dev).requires_grad_()
+        bm = pg.Basis("dct2", L)
+        Cm, Dm = bm.matrices()
+        res = []
+        plain_flops = 2.0 * Bsz * Din * Dh * 2 + 2.0 * Bsz * Dh * Dout * 3    # fwd + dW1 + fwd + dH + dW2
+        for r1, r2 in [(16, 64), (64, 64), (8, 16)]:
+            def it():
+                W1d.grad = None
+                W2d.grad = None
+                H = torch.nn.functional.gelu(proj_matmul(Xd, W1d, r1, bm, "bf16"), approximate="tanh")
+                Y = proj_matmul(H, W2d, r2, bm, "bf16")
+                loss = 0.5 * torch.mean((Y - Td) ** 2)
+                loss.backward()
+                return loss
+            t = autotune._time_ms(it, 5, warmup=2)
+            loss = float(it().item())
+            # FP64 reference loss through the oracle's closed form A Q B
+            H0 = oracle.gemm_proj_closed(X, W1, Cm, Dm, r1)
+            Hr = 0.5 * H0 * (1.0 + np.tanh(0.7978845608028654 * (H0 + 0.044715 * H0 ** 3)))
+            Yr = oracle.gemm_proj_closed(Hr, W2, Cm, Dm, r2)
+            loss_ref = 0.5 * float(np.mean((Yr - T) ** 2))
+            res.append({"r1": r1, "r2": r2, "prec": "bf16", "ms_fwd_bwd": round(t, 4),
+                        "exact_equiv_tflops": round(plain_flops / (t * 1e-3) / 1e12, 3),
+                        "loss": round(loss, 6), "loss_rel_err_vs_fp64": f3(abs(loss - loss_ref) / loss_ref)})
+        return res
+
+    section("sweep", sec_sweep)
+    section("precisions", sec_precisions)
+    section("plain", sec_plain)
+    section("conv", sec_conv)
+    section("batched", sec_batched)
+    section("mlp", sec_mlp)
 
     if not args.no_cpu:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(A, Bt, r)
     print(json.dumps(out), flush=True)
 
