@@ -302,7 +302,7 @@ def main():
         Cb, Db = bb.matrices()
         res = []
         for prec, rr in [("bf16x3", 4), ("bf16", 4), ("bf16", 16), ("fp8", 8), ("f16x3", 16)]:
-            cfg_b = autotune.tune_batched(As, Bs, rr, bb, prec=prec, reps=2, candidates=[0, 2, 4, 6])
+            cfg_b = autotune.tune_batched(As, Bs, rr, bb, prec=prec, reps=2, candidates=[0, 5, 6, 9])
             outs = pg.gemm_batched(As, Bs, rr, bb, prec=prec, tile_cfg=cfg_b)
             descs = pg._descs(As, Bs, outs)
             ws = torch.empty(pg.gemm_batched_workspace_bytes(descs, Lb, rr, prec, cfg_b), dtype=torch.uint8,

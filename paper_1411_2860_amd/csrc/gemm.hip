@@ -271,35 +271,188 @@ __device__ inline void gemm_tile(
             }
 }
 
+// The same workgroup tile with the operands staged through LDS: per k-block
+// the workgroup copies its BMB + BNB packed tiles (already in fragment order,
+// 1 KiB per plane, so the copy is a plain coalesced 16-byte-per-lane stream)
+// into one of two LDS stages while its waves run the matrix instructions on
+// fragments of the other stage.  Each tile is fetched from L2 once per
+// workgroup instead of once per wave, and the global loads of k-block k+1
+// overlap the MFMAs of k-block k.  16-byte lane formats only (not FP8).
 template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
+__device__ inline void gemm_tile_lds(
+    const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
+    const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
+    int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
+    float beta, int64_t tm, int64_t tn)
+{
+    using T = MT<PREC>;
+    using frag = typename T::frag;
+    using acc_t = typename T::acc;
+    constexpr int RB = T::RB, PL = T::PLANES;
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
+    constexpr int BMB = WM * WAVES_M, BNB = WN * WAVES_N;
+    constexpr int NTILE = (BMB + BNB) * PL;        // 1 KiB tiles per k-block
+    constexpr int NCH = NTILE * 64;                // 16-byte chunks per k-block
+    constexpr int PER_T = (NCH + NT - 1) / NT;
+    static_assert(sizeof(frag) == 16, "LDS path is for 16-byte lane formats");
+    (void)x_pb;
+    (void)y_pb;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    f32x4* lds = reinterpret_cast<f32x4*>(smem_raw);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+    const int64_t rbB = tm * BMB, cbB = tn * BNB;
+
+    // source of chunk c of a k-block: tile ti = c / 64 = blk * PL + pl
+    const char* src[PER_T];
+    bool ok[PER_T];
+#pragma unroll
+    for (int i = 0; i < PER_T; ++i) {
+        const int c = tid + i * NT;
+        const int ti = c / 64, lc = c % 64;
+        const int blk = ti / PL, pl = ti % PL;
+        ok[i] = false;
+        src[i] = X;
+        if (c < NCH) {
+            if (blk < BMB) {
+                const int64_t rb = rbB + blk;
+                ok[i] = rb < x_nrb;
+                src[i] = X + pl * x_plane + ((ok[i] ? rb : 0) * x_nkb * 64 + lc) * 16;
+            } else {
+                const int64_t cb = cbB + blk - BMB;
+                ok[i] = cb < y_nrb;
+                src[i] = Y + pl * y_plane + ((ok[i] ? cb : 0) * y_nkb * 64 + lc) * 16;
+            }
+        }
+    }
+    f32x4 stage[PER_T];
+    auto gload = [&](int64_t kb) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i)
+            stage[i] = ok[i] ? *reinterpret_cast<const f32x4*>(src[i] + kb * 1024) : f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+    auto swrite = [&](int s) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            const int c = tid + i * NT;
+            if (c < NCH) lds[s * NCH + c] = stage[i];
+        }
+    };
+
+    acc_t acc[WM][WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+#pragma unroll
+            for (int j = 0; j < T::NACC; ++j) acc[a][b][j] = 0;
+
+    // highest projection first (see gemm_tile)
+    if (nkb > 0) {
+        gload(nkb - 1);
+        swrite(0);
+    }
+    __syncthreads();
+    for (int64_t st = 0; st < nkb; ++st) {
+        const int s = (int)(st & 1);
+        if (st + 1 < nkb) gload(nkb - 2 - st);
+        frag fa[WM][PL], fb[WN][PL];
+#pragma unroll
+        for (int a = 0; a < WM; ++a)
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+                fa[a][pl] = *reinterpret_cast<const frag*>(&lds[s * NCH + ((wm * WM + a) * PL + pl) * 64 + lane]);
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+                fb[b][pl] = *reinterpret_cast<const frag*>(&lds[s * NCH + ((BMB + wn * WN + b) * PL + pl) * 64 + lane]);
+#pragma unroll
+        for (int a = 0; a < WM; ++a)
+#pragma unroll
+            for (int b = 0; b < WN; ++b) T::mma(acc[a][b], fa[a], fb[b]);
+        if (st + 1 < nkb) swrite(s ^ 1);
+        __syncthreads();
+    }
+
+    const int64_t rb0 = rbB + wm * WM, cb0 = cbB + wn * WN;
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+#pragma unroll
+            for (int j = 0; j < T::NACC; ++j) {
+                int row, col;
+                acc_pos<RB>(j, lane, row, col);
+                const int64_t p = (rb0 + a) * RB + row;
+                const int64_t q = (cb0 + b) * RB + col;
+                if (p < P && q < Q) {
+                    typename T::out_t v = (typename T::out_t)acc[a][b][j];
+                    if (beta != 0.0f) v += (typename T::out_t)beta * R[p * ldr + q];
+                    R[p * ldr + q] = v;
+                }
+            }
+}
+
+// Kernel body selector: KIND 0 = direct fragment loads, 1 = LDS-staged.
+template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+__device__ inline void gemm_any(
+    const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
+    const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
+    int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
+    float beta, int64_t tm, int64_t tn)
+{
+    if constexpr (KIND == 1 && sizeof(typename MT<PREC>::frag) == 16)
+        gemm_tile_lds<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
+                                                      nkb, P, Q, R, ldr, beta, tm, tn);
+    else
+        gemm_tile<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
+                                                  nkb, P, Q, R, ldr, beta, tm, tn);
+}
+
+template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+constexpr size_t gemm_lds_bytes()
+{
+    if constexpr (KIND == 1 && sizeof(typename MT<PREC>::frag) == 16)
+        return 2ull * (WM * WAVES_M + WN * WAVES_N) * MT<PREC>::PLANES * 1024;
+    return 0;
+}
+
+// OCC = minimum resident workgroups per CU the register allocation must allow.
+#define PJ_GEMM_BOUNDS __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
+
+template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
+__global__ PJ_GEMM_BOUNDS void gemm_kernel(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
     int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
     float beta, int64_t tiles_m, int64_t ntiles)
 {
     const int64_t tile = xcd_remap(blockIdx.x, ntiles);
-    gemm_tile<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb, nkb, P,
-                                              Q, R, ldr, beta, tile % tiles_m, tile / tiles_m);
+    gemm_any<KIND, PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
+                                                   nkb, P, Q, R, ldr, beta, tile % tiles_m, tile / tiles_m);
 }
 
 // Persistent grouped launch: workgroup b processes items b, b + grid, ... of
 // a list of (problem, tile) items sorted by decreasing contraction length, so
 // the longest tiles start first and the tail is made of short ones.
-template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_grouped_kernel(
+template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
+__global__ PJ_GEMM_BOUNDS void gemm_grouped_kernel(
     const GroupedProblem* __restrict__ probs, const GroupedItem* __restrict__ items, int64_t nitems)
 {
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const GroupedItem w = items[it];
         const GroupedProblem& p = probs[w.prob];
-        gemm_tile<PREC, WM, WN, WAVES_M, WAVES_N>(
+        gemm_any<KIND, PREC, WM, WN, WAVES_M, WAVES_N>(
             (const char*)p.X, p.x_nrb, p.x_nkb, p.x_plane, p.x_pb, (const char*)p.Y, p.y_nrb, p.y_nkb, p.y_plane,
             p.y_pb, p.nkb, p.P, p.Q, (typename MT<PREC>::out_t*)p.R, p.ldr, p.beta, w.tm, w.tn);
     }
 }
 
-template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
 int launch_gemm_t(const GemmArgs& a, hipStream_t s)
 {
     constexpr int RB = MT<PREC>::RB;
@@ -307,8 +460,9 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     const int64_t tiles_n = cdiv(a.gy.nrb, (int64_t)WAVES_N * WN);
     const int64_t ntiles = tiles_m * tiles_n;
     (void)RB;
-    hipLaunchKernelGGL((gemm_kernel<PREC, WM, WN, WAVES_M, WAVES_N>), dim3((unsigned)ntiles),
-                       dim3(64 * WAVES_M * WAVES_N), 0, s,
+    constexpr size_t lds = gemm_lds_bytes<KIND, PREC, WM, WN, WAVES_M, WAVES_N>();
+    hipLaunchKernelGGL((gemm_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>), dim3((unsigned)ntiles),
+                       dim3(64 * WAVES_M * WAVES_N), lds, s,
                        (const char*)a.X, a.gx.nrb, a.gx.nkb, a.gx.plane_bytes + a.gx.scale_plane, a.gx.plane_bytes,
                        (const char*)a.Y, a.gy.nrb, a.gy.nkb, a.gy.plane_bytes + a.gy.scale_plane, a.gy.plane_bytes,
                        a.nkb, a.P, a.Q, (typename MT<PREC>::out_t*)a.R, a.ldr, a.beta, tiles_m, ntiles);
@@ -317,32 +471,39 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
 
 }  // namespace
 
-// Tile configurations: (MFMA blocks per wave along M, along N, waves along M,
-// waves along N).  The workgroup tile is RB*WM*WAVES_M x RB*WN*WAVES_N.
-#define PJ_GEMM_CONFIGS(X) \
-    X(0, 2, 2, 2, 2)       \
-    X(1, 4, 2, 2, 2)       \
-    X(2, 2, 4, 2, 2)       \
-    X(3, 4, 4, 2, 2)       \
-    X(4, 2, 2, 1, 1)       \
-    X(5, 4, 4, 1, 1)       \
-    X(6, 1, 1, 2, 2)
+// Tile configurations: (kind: 0 direct fragment loads, 1 LDS-staged; MFMA
+// blocks per wave along M, along N; waves along M, along N; minimum resident
+// workgroups per CU).  The workgroup tile is RB*WM*WAVES_M x RB*WN*WAVES_N.
+// FP8 runs the LDS kinds as direct.
+#define PJ_GEMM_CONFIGS(X)   \
+    X(0, 0, 2, 2, 2, 2, 2)   \
+    X(1, 0, 4, 2, 2, 2, 1)   \
+    X(2, 0, 2, 4, 2, 2, 1)   \
+    X(3, 0, 4, 4, 2, 2, 1)   \
+    X(4, 0, 2, 2, 1, 1, 2)   \
+    X(5, 0, 1, 1, 2, 2, 2)   \
+    X(6, 1, 2, 2, 2, 2, 2)   \
+    X(7, 1, 2, 4, 2, 2, 1)   \
+    X(8, 1, 4, 2, 2, 2, 1)   \
+    X(9, 1, 2, 2, 2, 4, 1)   \
+    X(10, 1, 2, 2, 4, 2, 1)
 
 namespace {
 struct TileCfg { int wm, wn, wavm, wavn; };
 constexpr TileCfg kTileCfgs[] = {
-#define PJ_CFG_ROW(i, a, b, c, d) {a, b, c, d},
+#define PJ_CFG_ROW(i, k, a, b, c, d, o) {a, b, c, d},
     PJ_GEMM_CONFIGS(PJ_CFG_ROW)
 #undef PJ_CFG_ROW
 };
 constexpr int kNumTileCfgs = (int)(sizeof(kTileCfgs) / sizeof(kTileCfgs[0]));
 
-template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
 int launch_grouped_t(const GroupedProblem* probs, const GroupedItem* items, int64_t nitems, int64_t grid,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL((gemm_grouped_kernel<PREC, WM, WN, WAVES_M, WAVES_N>), dim3((unsigned)grid),
-                       dim3(64 * WAVES_M * WAVES_N), 0, s, probs, items, nitems);
+    constexpr size_t lds = gemm_lds_bytes<KIND, PREC, WM, WN, WAVES_M, WAVES_N>();
+    hipLaunchKernelGGL((gemm_grouped_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>), dim3((unsigned)grid),
+                       dim3(64 * WAVES_M * WAVES_N), lds, s, probs, items, nitems);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -351,8 +512,8 @@ int launch_grouped_cfg(const GroupedProblem* probs, const GroupedItem* items, in
                        hipStream_t s)
 {
     switch (cfg) {
-#define PJ_CFG_CASE(i, a_, b_, c_, d_) \
-    case i: return launch_grouped_t<PREC, a_, b_, c_, d_>(probs, items, nitems, grid, s);
+#define PJ_CFG_CASE(i, k_, a_, b_, c_, d_, o_) \
+    case i: return launch_grouped_t<k_, PREC, a_, b_, c_, d_, o_>(probs, items, nitems, grid, s);
         PJ_GEMM_CONFIGS(PJ_CFG_CASE)
 #undef PJ_CFG_CASE
     default: return -2;
@@ -363,8 +524,8 @@ template <int PREC>
 int launch_cfg(const GemmArgs& a, int cfg, hipStream_t s)
 {
     switch (cfg) {
-#define PJ_CFG_CASE(i, a_, b_, c_, d_) \
-    case i: return launch_gemm_t<PREC, a_, b_, c_, d_>(a, s);
+#define PJ_CFG_CASE(i, k_, a_, b_, c_, d_, o_) \
+    case i: return launch_gemm_t<k_, PREC, a_, b_, c_, d_, o_>(a, s);
         PJ_GEMM_CONFIGS(PJ_CFG_CASE)
 #undef PJ_CFG_CASE
     default: return -2;
@@ -405,9 +566,11 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
     if (prec == P_F64) return 3;
     // small problems: smaller tiles so that the grid still covers the chip
     const int64_t tiles128 = cdiv(P, 128) * cdiv(Q, 128);
-    if (tiles128 < 256) return 6;
-    if (prec == P_F32 || prec == P_BF16X3 || prec == P_F16X3) return 2;   // 128 x 256
-    return 0;
+    if (tiles128 < 256) return 5;
+    if (prec == P_FP8 || prec == P_FP8X2) return 0;
+    if (prec == P_F32) return 6;                                   // LDS 128 x 128
+    if (prec == P_BF16X3 || prec == P_F16X3) return 9;             // LDS 128 x 256, 8 waves
+    return 6;
 }
 
 int launch_gemm(int prec, const GemmArgs& a, int cfg, hipStream_t s)

@@ -43,6 +43,7 @@ struct PackJob {
     char* out;
     int64_t nkb, Gp, plane_stride, plane_bytes, plain_ld;
     int64_t nrb, ngt;   // row blocks, group tiles (Gp / KB)
+    int64_t nrt;        // row tiles of the compute mapping
     int TC, TCp, JS, RS;
 };
 
@@ -61,43 +62,6 @@ __device__ inline unsigned fp8_e4m3_rne(float v)
         code = ((((b >> 23) & 0xFFu) - 120u) << 3) | ((b >> 20) & 7u);
     }
     return sign | code;
-}
-
-// Quantises 32 values to FP8 with one power-of-two (E8M0) scale 2^e chosen
-// so that the largest magnitude lands in (224, 448]; returns the scale byte
-// e + 127 and writes the 32 codes into w.
-template <typename TIn>
-__device__ inline unsigned quant_block32(const TIn* v, i32x8& w, float* deq)
-{
-    float amax = 0.0f;
-#pragma unroll
-    for (int e = 0; e < 32; ++e) amax = fmaxf(amax, fabsf((float)v[e]));
-    int ex = -127;
-    if (amax > 0.0f) {
-        int f;
-        const float m = frexpf(amax / 448.0f, &f);   // amax / 448 = m 2^f, m in [0.5, 1)
-        ex = (m == 0.5f) ? f - 1 : f;                  // ceil(log2(amax / 448))
-        ex = ex < -127 ? -127 : (ex > 127 ? 127 : ex);
-    }
-    const float inv = ldexpf(1.0f, -ex), sc = ldexpf(1.0f, ex);
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        unsigned word = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float x = (float)v[4 * d + q] * inv;
-            const unsigned c = fp8_e4m3_rne(fminf(fmaxf(x, -448.0f), 448.0f));
-            word |= c << (8 * q);
-            if (deq) {
-                const unsigned mag = c & 0x7Fu;
-                const float val = (mag < 8u) ? (float)mag * 0.001953125f
-                                             : ldexpf(1.0f + (float)(mag & 7u) * 0.125f, (int)(mag >> 3) - 7);
-                deq[4 * d + q] = ((c & 0x80u) ? -val : val) * sc;
-            }
-        }
-        w[d] = (int)word;
-    }
-    return (unsigned)(ex + 127);
 }
 
 // ---- conversion of E accumulated values into one lane vector -------------
@@ -138,35 +102,6 @@ __device__ inline void store_lane(char* __restrict__ out, int64_t off, int64_t p
         }
         *reinterpret_cast<f16x8*>(out + off) = hi;
         if constexpr (PREC == P_F16X3) *reinterpret_cast<f16x8*>(out + plane_stride + off) = lo;
-    } else if constexpr (PREC == P_FP8 || PREC == P_FP8X2) {
-        static_assert(E == 32, "fp8 lane vector");
-        // The block-scaled 8-bit matrix instruction reads, for row `row` of a
-        // 64-index tile, MX block h (indices 32h .. 32h+31) as bytes 16h..16h+15
-        // of lane `row` followed by bytes 16h..16h+15 of lane 32 + row, and
-        // takes its scale from lane 32h + row.  The thread of lane (g, row)
-        // holds exactly block g, so it quantises its 32 values with one scale
-        // and scatters them as two 16-byte halves.
-        const int64_t tile = off / (64 * 32);
-        const int lane = (int)(off / 32 % 64);
-        const int g = lane / 32, row = lane % 32;
-        const int64_t lo_half = (tile * 64 + row) * 32 + 16 * g;
-        const int64_t hi_half = (tile * 64 + 32 + row) * 32 + 16 * g;
-        i32x8 w;
-        float deq[32];
-        const unsigned s = quant_block32<TIn>(v, w, PREC == P_FP8X2 ? deq : nullptr);
-        *reinterpret_cast<i32x4*>(out + lo_half) = i32x4{w[0], w[1], w[2], w[3]};
-        *reinterpret_cast<i32x4*>(out + hi_half) = i32x4{w[4], w[5], w[6], w[7]};
-        out[plane_bytes + tile * 64 + lane] = (char)s;
-        if constexpr (PREC == P_FP8X2) {
-            float res[32];
-#pragma unroll
-            for (int e = 0; e < 32; ++e) res[e] = (float)v[e] - deq[e];
-            i32x8 w2;
-            const unsigned s2 = quant_block32<float>(res, w2, nullptr);
-            *reinterpret_cast<i32x4*>(out + plane_stride + lo_half) = i32x4{w2[0], w2[1], w2[2], w2[3]};
-            *reinterpret_cast<i32x4*>(out + plane_stride + hi_half) = i32x4{w2[4], w2[5], w2[6], w2[7]};
-            out[plane_stride + plane_bytes + tile * 64 + lane] = (char)s2;
-        }
     }
 }
 
@@ -175,38 +110,136 @@ template <> struct Vec4<float> { using type = f32x4; };
 template <> struct Vec4<double> { using type = f64x4; };
 
 // ---- the kernel -----------------------------------------------------------
+// Thread mapping of the projection: each wave covers TRc rows x KB groups,
+// lane (row, g) computing Ec consecutive groups; 4 waves split the
+// projections.  For FP8 a lane computes one eighth of a 64-group tile row so
+// that the 4 lanes of an MX block are adjacent (their maximum is combined
+// with lane shuffles).
+template <int PREC> struct Cmap {
+    static constexpr Layout ly = layout_of(PREC);
+    static constexpr int Ec = (ly.E > 8) ? 8 : ly.E;
+    static constexpr int NGc = ly.KB / Ec;
+    static constexpr int TRc = 64 / NGc;
+};
+
+__device__ inline unsigned fp8_exp_byte(float amax, float& inv, float& sc)
+{
+    int ex = -127;
+    if (amax > 0.0f) {
+        int f;
+        const float m = frexpf(amax / 448.0f, &f);   // amax / 448 = m 2^f, m in [0.5, 1)
+        ex = (m == 0.5f) ? f - 1 : f;                  // ceil(log2(amax / 448))
+        ex = ex < -127 ? -127 : (ex > 127 ? 127 : ex);
+    }
+    inv = ldexpf(1.0f, -ex);
+    sc = ldexpf(1.0f, ex);
+    return (unsigned)(ex + 127);
+}
+
+__device__ inline float fp8_decode(unsigned c)
+{
+    const unsigned mag = c & 0x7Fu;
+    const float val = (mag < 8u) ? (float)mag * 0.001953125f
+                                 : ldexpf(1.0f + (float)(mag & 7u) * 0.125f, (int)(mag >> 3) - 7);
+    return (c & 0x80u) ? -val : val;
+}
+
+// 8 values of one MX block quarter: codes (2 words) with the block's scale;
+// optionally the dequantised values.
+__device__ inline void fp8_encode8(const float* v, float inv, float sc, unsigned& w0, unsigned& w1, float* deq)
+{
+    w0 = w1 = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float x = fminf(fmaxf(v[e] * inv, -448.0f), 448.0f);
+        const unsigned c = fp8_e4m3_rne(x);
+        if (e < 4) w0 |= c << (8 * e);
+        else w1 |= c << (8 * (e - 4));
+        if (deq) deq[e] = fp8_decode(c) * sc;
+    }
+}
+
+__device__ inline float quad_max(float a)
+{
+    a = fmaxf(a, __shfl_xor(a, 1));
+    a = fmaxf(a, __shfl_xor(a, 2));
+    return a;
+}
+
+// One FP8 (x2) lane quarter: lane (row, g) of the compute mapping holds
+// indices 8g .. 8g+7 of a 64-index tile row, i.e. quarter g % 4 of MX block
+// g / 4.  The instruction reads block h of row `row` as bytes 16h..16h+15 of
+// lane row (indices 32h..32h+15) and of lane 32 + row (32h+16..32h+31).
+template <int PREC>
+__device__ inline void store_fp8_quarter(char* __restrict__ out, int64_t tile, int rib, int g, int64_t plane_stride,
+                                         int64_t plane_bytes, const float (&v)[8])
+{
+    const int h = g / 4, sub = g % 4;
+    const int lane_dst = (sub < 2) ? rib : 32 + rib;
+    const int64_t off = (tile * 64 + lane_dst) * 32 + 16 * h + 8 * (sub % 2);
+    float amax = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) amax = fmaxf(amax, fabsf(v[e]));
+    amax = quad_max(amax);
+    float inv, sc;
+    const unsigned s = fp8_exp_byte(amax, inv, sc);
+    unsigned w0, w1;
+    float deq[8];
+    fp8_encode8(v, inv, sc, w0, w1, PREC == P_FP8X2 ? deq : nullptr);
+    *reinterpret_cast<uint2*>(out + off) = make_uint2(w0, w1);
+    if (sub == 0) out[plane_bytes + tile * 64 + 32 * h + rib] = (char)s;
+    if constexpr (PREC == P_FP8X2) {
+        float res[8];
+        float rmax = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            res[e] = v[e] - deq[e];
+            rmax = fmaxf(rmax, fabsf(res[e]));
+        }
+        rmax = quad_max(rmax);
+        const unsigned s2 = fp8_exp_byte(rmax, inv, sc);
+        fp8_encode8(res, inv, sc, w0, w1, nullptr);
+        *reinterpret_cast<uint2*>(out + plane_stride + off) = make_uint2(w0, w1);
+        if (sub == 0) out[plane_stride + plane_bytes + tile * 64 + 32 * h + rib] = (char)s2;
+    }
+}
+
 template <typename TIn, int PREC, int RL, int NCH>
 __device__ inline void pack_tile(const PackJob<TIn>& J, int64_t tix)
 {
     constexpr Layout ly = layout_of(PREC);
-    constexpr int TR = ly.RB, KB = ly.KB, E = ly.E;
+    constexpr int KB = ly.KB, RB = ly.RB;
+    constexpr int Ec = Cmap<PREC>::Ec, NGc = Cmap<PREC>::NGc, TRc = Cmap<PREC>::TRc;
     using V4 = typename Vec4<TIn>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     TIn* lds = reinterpret_cast<TIn*>(smem_raw);
 
-    const int64_t rbi = tix / J.ngt;
+    const int64_t rti = tix / J.ngt;               // row tile of TRc rows
     const int64_t j0 = (tix % J.ngt) * KB;
-    const int64_t p0 = rbi * TR;
+    const int64_t p0 = rti * TRc;
+    const int64_t rbi = p0 / RB;                   // row block of the packed operand
+    const int rib0 = (int)(p0 % RB);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int row = lane % TR, g = lane / TR;
+    const int row = lane / NGc, g = lane % NGc;
     const int L = J.L, r = J.r, TC = J.TC, TCp = J.TCp, JS = J.JS, RS = J.RS;
     const TIn* __restrict__ X = J.X;
     const TIn* __restrict__ coef = J.coef;
 
     for (int lp = 0; lp < r; lp += 4 * NCH * RL) {
-        TIn acc[NCH][RL][E];
+        TIn acc[NCH][RL][Ec];
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
 #pragma unroll
             for (int q = 0; q < RL; ++q)
 #pragma unroll
-                for (int e = 0; e < E; ++e) acc[c][q][e] = (TIn)0;
+                for (int e = 0; e < Ec; ++e) acc[c][q][e] = (TIn)0;
 
         for (int t0 = 0; t0 < L; t0 += TC) {
             __syncthreads();
-            if (J.vec4) {
-                const int n4 = TR * KB * (TC / 4);
+            if (J.vec4 && !J.trans) {
+                // 16-byte loads along the contiguous contraction index
+                const int n4 = TRc * KB * (TC / 4);
                 for (int idx = threadIdx.x; idx < n4; idx += kPackThreads) {
                     const int tt4 = idx % (TC / 4);
                     const int q = idx / (TC / 4);
@@ -217,8 +250,38 @@ __device__ inline void pack_tile(const PackJob<TIn>& J, int64_t tix)
                     if (p < J.P && k < J.K) v = *reinterpret_cast<const V4*>(X + p * J.ld + k);
                     *reinterpret_cast<V4*>(lds + rr * RS + jj * JS + 4 * tt4) = v;
                 }
+            } else if (J.vec4) {
+                // strided source: 4 rows x 4 indices per thread, 16-byte loads
+                // along the rows, transposed in registers
+                const int n16 = (TRc / 4) * KB * (TC / 4);
+                for (int idx = threadIdx.x; idx < n16; idx += kPackThreads) {
+                    const int rr4 = idx % (TRc / 4);
+                    const int q = idx / (TRc / 4);
+                    const int tt4 = q % (TC / 4), jj = q / (TC / 4);
+                    const int64_t p = p0 + 4 * rr4;
+                    const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
+                    V4 col[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        col[i] = V4{0, 0, 0, 0};
+                        if (k + i < J.K) {
+                            if (p + 3 < J.P) {
+                                col[i] = *reinterpret_cast<const V4*>(X + (k + i) * J.ld + p);
+                            } else {
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    if (p + u < J.P) col[i][u] = X[(k + i) * J.ld + p + u];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const V4 w = {col[0][u], col[1][u], col[2][u], col[3][u]};
+                        *reinterpret_cast<V4*>(lds + (4 * rr4 + u) * RS + jj * JS + 4 * tt4) = w;
+                    }
+                }
             } else {
-                const int n1 = TR * KB * TCp;
+                const int n1 = TRc * KB * TCp;
                 for (int idx = threadIdx.x; idx < n1; idx += kPackThreads) {
                     int rr, jj, tt;
                     if (!J.trans) {
@@ -227,8 +290,8 @@ __device__ inline void pack_tile(const PackJob<TIn>& J, int64_t tix)
                         jj = q % KB;
                         rr = q / KB;
                     } else {
-                        rr = idx % TR;
-                        const int q = idx / TR;
+                        rr = idx % TRc;
+                        const int q = idx / TRc;
                         tt = q % TCp;
                         jj = q / TCp;
                     }
@@ -254,8 +317,8 @@ __device__ inline void pack_tile(const PackJob<TIn>& J, int64_t tix)
                                                                            : (TIn)0;
                 }
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const V4 v = *reinterpret_cast<const V4*>(lds + row * RS + (g * E + e) * JS + 4 * tt4);
+                for (int e = 0; e < Ec; ++e) {
+                    const V4 v = *reinterpret_cast<const V4*>(lds + row * RS + (g * Ec + e) * JS + 4 * tt4);
 #pragma unroll
                     for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -269,23 +332,33 @@ __device__ inline void pack_tile(const PackJob<TIn>& J, int64_t tix)
             }
         }
 
+        const int rib = rib0 + row;   // row within the packed row block
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int lb = lp + (wave + 4 * c) * RL;
 #pragma unroll
             for (int q = 0; q < RL; ++q) {
                 const int l = lb + q;
+                if (l >= r) continue;   // wave-uniform
                 if constexpr (PREC == P_PLAIN32 || PREC == P_PLAIN64) {
                     const int64_t p = p0 + row;
-                    if (l < r && p < J.P) {
-                        TIn* dst = reinterpret_cast<TIn*>(J.out) + p * J.plain_ld + (int64_t)l * J.Gp + j0 + g * E;
+                    if (p < J.P) {
+                        TIn* dst = reinterpret_cast<TIn*>(J.out) + p * J.plain_ld + (int64_t)l * J.Gp + j0 + g * Ec;
 #pragma unroll
-                        for (int e = 0; e < E; ++e) dst[e] = acc[c][q][e];
+                        for (int e = 0; e < Ec; ++e) dst[e] = acc[c][q][e];
                     }
-                } else if (l < r) {
+                } else {
                     const int64_t kbi = ((int64_t)l * J.Gp + j0) / KB;
-                    const int64_t off = ((rbi * J.nkb + kbi) * 64 + lane) * ly.LB;
-                    store_lane<PREC, E, TIn>(J.out, off, J.plane_stride, J.plane_bytes, acc[c][q]);
+                    const int64_t tile = rbi * J.nkb + kbi;
+                    if constexpr (PREC == P_FP8 || PREC == P_FP8X2) {
+                        float v8[8];
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) v8[e] = (float)acc[c][q][e];
+                        store_fp8_quarter<PREC>(J.out, tile, rib, g, J.plane_stride, J.plane_bytes, v8);
+                    } else {
+                        const int64_t off = (tile * 64 + g * RB + rib) * ly.LB;
+                        store_lane<PREC, Ec, TIn>(J.out, off, J.plane_stride, J.plane_bytes, acc[c][q]);
+                    }
                 }
             }
         }
@@ -325,8 +398,9 @@ PackJob<TIn> make_job(const PackArgs& a)
     j.X = (const TIn*)a.X;
     j.ld = a.ld;
     j.trans = a.trans;
-    j.vec4 = !a.trans && a.L % 4 == 0 && a.ld % 4 == 0 && a.K % 4 == 0 &&
-             ((uintptr_t)a.X % (4 * sizeof(TIn))) == 0;
+    // 16-byte loads: along k (contiguous source) or along the rows (strided)
+    j.vec4 = a.L % 4 == 0 && a.ld % 4 == 0 && ((uintptr_t)a.X % (4 * sizeof(TIn))) == 0 &&
+             (a.trans ? true : a.K % 4 == 0);
     j.P = a.P;
     j.K = a.K;
     j.L = a.L;
@@ -340,11 +414,13 @@ PackJob<TIn> make_job(const PackArgs& a)
     j.plain_ld = a.plain_ld;
     j.nrb = g.nrb;
     j.ngt = g.Gp / ly.KB;
+    // whole row blocks, so that padding rows are written (as zeros) too
+    j.nrt = g.nrb * (ly.RB / Cmap<PREC>::TRc);
     // chunk of t staged per round: the largest divisor of L whose padded tile
     // fits the LDS budget (a multiple of 4 when 16-byte loads are used)
     auto lds_of = [&](int tc) {
         const int tcp = (tc + 3) / 4 * 4;
-        return (size_t)ly.RB * ((size_t)ly.KB * (tcp + 4) + 4) * sizeof(TIn);
+        return (size_t)Cmap<PREC>::TRc * ((size_t)ly.KB * (tcp + 4) + 4) * sizeof(TIn);
     };
     int TC = a.L;
     while (TC > 1 && (lds_of(TC) > (size_t)kPackLdsBytes || a.L % TC != 0 || (j.vec4 && TC % 4 != 0))) --TC;
@@ -362,10 +438,11 @@ int launch_t(const PackArgs* a, int n, hipStream_t s)
     constexpr Layout ly = layout_of(PREC);
     PackJob<TIn> ja = make_job<TIn, PREC>(a[0]);
     PackJob<TIn> jb = n > 1 ? make_job<TIn, PREC>(a[1]) : ja;
-    const int64_t na = ja.nrb * ja.ngt;
-    const int64_t nb = n > 1 ? jb.nrb * jb.ngt : 0;
+    const int64_t na = ja.nrt * ja.ngt;
+    const int64_t nb = n > 1 ? jb.nrt * jb.ngt : 0;
     const int rs = ja.RS > jb.RS ? ja.RS : jb.RS;
-    const size_t lds = (size_t)ly.RB * rs * sizeof(TIn);
+    const size_t lds = (size_t)Cmap<PREC>::TRc * rs * sizeof(TIn);
+    (void)ly;
     if (na + nb > 0x7fffffff) return -2;
     hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH>), dim3((unsigned)(na + nb)), dim3(kPackThreads), lds, s,
                        ja, jb, na);
@@ -396,7 +473,7 @@ int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
     int rs = 0;
     for (int i = 0; i < n; ++i) {
         jobs[i] = make_job<TIn, PREC>(a[i]);
-        prefix[i + 1] = prefix[i] + jobs[i].nrb * jobs[i].ngt;
+        prefix[i + 1] = prefix[i] + jobs[i].nrt * jobs[i].ngt;
         rs = jobs[i].RS > rs ? jobs[i].RS : rs;
     }
     if (prefix[n] > 0x7fffffff || prefix[n] == 0) return -2;
@@ -406,7 +483,8 @@ int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
     if (hipMemcpyAsync(t + rup(jb, 256), prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return -1;
-    const size_t lds = (size_t)ly.RB * rs * sizeof(TIn);
+    const size_t lds = (size_t)Cmap<PREC>::TRc * rs * sizeof(TIn);
+    (void)ly;
     hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH>), dim3((unsigned)prefix[n]), dim3(kPackThreads),
                        lds, s, (const PackJob<TIn>*)t, (const int64_t*)(t + rup(jb, 256)), n);
     return hipGetLastError() == hipSuccess ? 0 : -1;

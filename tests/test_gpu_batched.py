@@ -60,7 +60,7 @@ def test_small_uneven_batch(pg, prec, r):
         _tol.assert_within(R.double().cpu().numpy(), ref, _bound(prec, A, B, C, D, r, L), f"problem {i} {prec} r={r}")
 
 
-@pytest.mark.parametrize("cfg", range(7))
+@pytest.mark.parametrize("cfg", range(11))
 def test_every_tile_config_and_layouts(pg, cfg):
     """Each workgroup tile configuration of the persistent launch, with mixed
     layouts: A stored transposed, B stored transposed."""
@@ -70,11 +70,14 @@ def test_every_tile_config_and_layouts(pg, cfg):
     C, D = basis.matrices()
     Ad = [torch.from_numpy(np.ascontiguousarray(a.T)).float().cuda() for a in As]
     Bd = [torch.from_numpy(np.ascontiguousarray(b.T)).float().cuda() for b in Bs]
-    outs = pg.gemm_batched(Ad, Bd, r, basis, prec="f32", transA=True, transB=True, tile_cfg=cfg)
-    torch.cuda.synchronize()
-    for i, (A, B, R) in enumerate(zip(As, Bs, outs)):
-        ref = oracle.gemm_proj(A, B, C, D, r)
-        _tol.assert_within(R.double().cpu().numpy(), ref, _bound("f32", A, B, C, D, r, L), f"cfg {cfg} problem {i}")
+    assert cfg < len(pg.tile_configs("f32"))
+    for prec in ("f32", "bf16x3"):
+        outs = pg.gemm_batched(Ad, Bd, r, basis, prec=prec, transA=True, transB=True, tile_cfg=cfg)
+        torch.cuda.synchronize()
+        for i, (A, B, R) in enumerate(zip(As, Bs, outs)):
+            ref = oracle.gemm_proj(A, B, C, D, r)
+            _tol.assert_within(R.double().cpu().numpy(), ref, _bound(prec, A, B, C, D, r, L),
+                               f"cfg {cfg} {prec} problem {i}")
 
 
 def test_batched_equals_single_calls(pg):
