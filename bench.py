@@ -38,7 +38,7 @@ PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500
         "fp8": 5000.0, "fp8x2": 5000.0}      # dense MFMA TFLOP/s of the operand format
 MFMA_PER_PRODUCT = {"bf16x3": 3, "f16x3": 3, "fp8x2": 3}
 PEAK_HBM = 8000.0                            # GB/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f32_recognition_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f32_recognition_traffic.md")
 SECTIONS = ["sweep", "precisions", "plain", "conv", "batched", "mlp"]
 
 
@@ -121,11 +121,17 @@ def main():
     C, D = basis.matrices()
 
     if args.profile:
-        # a plain copy of known size, for scaling the HBM byte counters
-        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        # plain copies of known size (256 MiB read + 256 MiB written), for
+        # scaling the HBM byte counters: the runtime's device-to-device copy
+        # and an elementwise FP32 kernel
+        src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
+        srcf = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dstf = torch.empty_like(srcf)
+        torch.add(srcf, 1.0, out=dstf)
         torch.cuda.synchronize()
+        del src, dst, srcf, dstf
 
     def timed(r, prec, steps, warmup, b=basis, Lb=L):
         cfg = autotune.tune_gemm(M, W, K, Lb, r, prec, reps=3, basis=b)
@@ -177,7 +183,7 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
+            tr = json.loads(f.read().split("```json", 1)[1].split("```", 1)[0])
         if tr.get("sources_hash") == kernel_sources_hash() and tr.get("r") == r:
             traffic = tr.get("gemm_bytes_per_launch")
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.h"
+#include "conv.h"
 
 using namespace pj;
 
@@ -675,7 +676,9 @@ int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, c
     if (W < 1 || N < 1 || N > W) return PJ_ERR_SHAPE;
     if (prec != PJ_F32) return PJ_ERR_UNSUPPORTED;
     const ConvGeom g = conv_geom(W, N, b->L, r);
-    if (g.tiles_m * 4 > 0x7fffffff || g.k_nrb * g.k_nkb * 64 / 256 > 0x7fffffff) return PJ_ERR_UNSUPPORTED;
+    if (g.tiles_m * g.tiles_n > 0x7fffffff || g.k_nrb * g.k_nkb * 64 / 256 > 0x7fffffff || cdiv(g.nout, 256) > 0x7fffffff ||
+        cdiv(g.nbp, 64) > 0x7fffffff || g.ncp * b->L > 0x7fffffff)
+        return PJ_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < (size_t)g.total) return PJ_ERR_WORKSPACE;
     if (!b->on_device) return PJ_ERR_HIP;
     ConvArgs a;

@@ -17,112 +17,266 @@
 // operand H[a, (l,c)] = sc_l[a + c] is a Hankel matrix: its MFMA fragments are
 // read straight from the projected signal (small, cache resident), and the
 // right operand K is packed once in the same fragment order as the GEMM's.
-#include "common.h"
+#include <algorithm>
+
+#include "conv.h"
 
 namespace pj {
 
 namespace {
 
-constexpr int kSigBlocks = 32;   // signal blocks per workgroup in step 1
+constexpr int kMaxConvL = 256;   // largest block length the library accepts
+
+// Steps 1 and 2 are small dense contractions over the L samples of a block
+// (resp. the L taps of a phase) and run on the FP32 matrix cores: one wave
+// computes a 32 x 32 tile (32 projections x 32 blocks, resp. 32 lags) with
+// 32x32x2 MFMAs, 8 contraction indices per lane step (lane half g takes
+// indices 4g .. 4g + 3 of each group of 8, element e in MFMA number e).
+
+// Copies the 32 columns l0 .. l0 + 31 of an L x L row-major FP32 matrix into
+// LDS as [row][32] (rows up to the next multiple of 8 of L, zeros past L and
+// past column r), with every load of a thread issued before its first store.
+template <int NT>
+__device__ __forceinline__ void stage_slice(const float* __restrict__ M, int L, int r, int l0, float* __restrict__ S)
+{
+    constexpr int SPT = kMaxConvL * 32 / NT;
+    const int tid = threadIdx.x;
+    const int lim = ((L + 7) / 8) * 8 * 32;
+    float v[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int idx = tid + j * NT;
+        const int t = idx / 32, l = idx % 32;
+        v[j] = (t < L && l0 + l < r) ? M[(int64_t)t * L + l0 + l] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int idx = tid + j * NT;
+        if (idx < lim) S[idx] = v[j];
+    }
+}
 
 // ---- step 1: block projection of the signal ---------------------------------
-// Thread t handles projection l = t % LR and blocks b = t / LR + k * (256 / LR)
-// of the workgroup's kSigBlocks blocks.  The blocks are staged in LDS with a
-// padded row (L + 1) so that lanes reading different blocks hit different
-// banks.
-template <int BPT>
-__global__ __launch_bounds__(256) void sig_project_kernel(
-    const float* __restrict__ s, int64_t W, int L, int r, int LR, const float* __restrict__ C,
+// sc_l[i] = sum_t C[t, l] s[iL + t]: A = C^T (32 projections from the LDS copy
+// of C[:, l0 : l0 + 32]), B = the blocks (lane = block; its samples stream
+// through a 4-deep register ring, 16 bytes at a time when aligned).
+// Accumulator register j of a lane holds projection 8 (j / 4) + 4 g + (j % 4)
+// of block lane % 32, so each register writes 32 consecutive entries of one
+// row sc_l[.].
+template <bool VEC>
+__device__ __forceinline__ f32x4 sig_chunk(const float* __restrict__ s, int64_t W, int L, int64_t nb, int ch, int g)
+{
+    f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int t = 8 * ch + 4 * g;
+    const int64_t n = nb + t;
+    if (VEC && t + 3 < L && n + 3 < W) {
+        v = *reinterpret_cast<const f32x4*>(s + n);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (t + e < L && n + e < W) ? s[n + e] : 0.0f;
+    }
+    return v;
+}
+
+template <int NW, bool VEC>
+__global__ __launch_bounds__(64 * NW) void sig_project_kernel(
+    const float* __restrict__ s, int64_t W, int L, int r, const float* __restrict__ C,
     float* __restrict__ sc, int64_t nbp)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    float* lds = reinterpret_cast<float*>(smem_raw);
-    const int64_t i0 = (int64_t)blockIdx.x * kSigBlocks;
-    const int LP = L + 1;
-    for (int idx = threadIdx.x; idx < kSigBlocks * L; idx += 256) {
-        const int blk = idx / L, t = idx % L;
-        const int64_t n = (i0 + blk) * L + t;
-        lds[blk * LP + t] = (n < W) ? s[n] : 0.0f;
-    }
+    constexpr int PD = 4;                          // chunks in flight per lane
+    __shared__ float Cs[kMaxConvL * 32];          // [t][l - l0]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 31, g = lane >> 5;
+    const int l0 = blockIdx.y * 32;
+    const int64_t i0 = ((int64_t)blockIdx.x * NW + wave) * 32;
+    const int nch = (L + 7) / 8;
+    const int64_t nb = (i0 + row) * L;
+
+    f32x4 ring[PD];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) ring[j] = j < nch ? sig_chunk<VEC>(s, W, L, nb, j, g) : f32x4{0.f, 0.f, 0.f, 0.f};
+    stage_slice<64 * NW>(C, L, r, l0, Cs);
     __syncthreads();
-    const int l = threadIdx.x % LR;
-    const int bg = threadIdx.x / LR, BG = 256 / LR;
-    if (l >= r) return;
-    float acc[BPT];
+
+    f32x16 acc;
 #pragma unroll
-    for (int k = 0; k < BPT; ++k) acc[k] = 0.0f;
-    for (int t = 0; t < L; ++t) {
-        const float cf = C[t * L + l];
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+    for (int ch0 = 0; ch0 < nch; ch0 += PD) {
 #pragma unroll
-        for (int k = 0; k < BPT; ++k) {
-            const int blk = bg + k * BG;
-            if (blk < kSigBlocks) acc[k] += lds[blk * LP + t] * cf;
+        for (int j = 0; j < PD; ++j) {
+            const int ch = ch0 + j;
+            if (ch < nch) {
+                const f32x4 x = ring[j];
+                if (ch + PD < nch) ring[j] = sig_chunk<VEC>(s, W, L, nb, ch + PD, g);
+                const float* cp = &Cs[(8 * ch + 4 * g) * 32 + row];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[0], x[0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[32], x[1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[64], x[2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[96], x[3], acc, 0, 0, 0);
+            }
         }
     }
+    const int64_t i = i0 + row;
 #pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-        const int blk = bg + k * BG;
-        const int64_t i = i0 + blk;
-        if (blk < kSigBlocks && i < nbp) sc[(int64_t)l * nbp + i] = acc[k];
+    for (int j = 0; j < 16; ++j) {
+        const int l = l0 + 8 * (j >> 2) + 4 * g + (j & 3);
+        if (l < r && i < nbp) sc[(int64_t)l * nbp + i] = acc[j];
     }
 }
 
 // ---- step 2: kernel projected at every phase, packed as the right operand ---
-// Packed like a GEMM operand (fragment order, FP32 tiles of 32 rows x 8):
-// rows are the phases b < L, the contraction index is k = l * ncp + c.
-__global__ __launch_bounds__(256) void kmat_pack_kernel(
-    const float* __restrict__ k, int N, int reverse, int L, int r, int ncp, const float* __restrict__ DT,
-    char* __restrict__ out, int64_t nrb, int64_t nkb)
+// kd_l[q] = sum_u D[l, u] k'(q + u) for the lags q = e - (L - 1), e < ncp L:
+// A = D (32 projections from the LDS copy of D^T[:, l0 : l0 + 32]), B = the
+// Hankel matrix of k' (lane = lag, its 4 taps read from the LDS window of
+// k').  Lag q is phase b = L - 1 - (e mod L) of kernel block c = e / L; the
+// result goes straight to the packed right operand (fragment order, FP32
+// tiles of 32 rows x 8): row b, contraction index l * ncp + c.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void kphase_kernel(
+    const float* __restrict__ k, int64_t N, int reverse, int L, int r, int64_t ncp, const float* __restrict__ DT,
+    char* __restrict__ out, int64_t k_nkb)
 {
-    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;   // lane vector index
-    const int64_t total = nrb * nkb * 64;
-    if (v >= total) return;
-    const int lane = (int)(v % 64);
-    const int64_t tile = v / 64;
-    const int64_t kb = tile % nkb, cb = tile / nkb;
-    const int col = lane % 32, g = lane / 32;
-    const int b = (int)(cb * 32 + col);
-    const int64_t kk = kb * 8 + g * 4;     // first of 4 consecutive contraction indices
-    const int l = (int)(kk / ncp);
-    const int c0 = (int)(kk % ncp);
-    f32x4 w = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (b < L && l < r) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t q = (int64_t)(c0 + e) * L - b;
-            float acc = 0.0f;
-            for (int u = 0; u < L; ++u) {
-                const int64_t n = q + u;
-                if (n >= 0 && n < N) {
-                    const float kv = reverse ? k[N - 1 - n] : k[n];
-                    acc += DT[u * L + l] * kv;
-                }
-            }
-            w[e] = acc;
-        }
+    constexpr int QW = 32 * NW;
+    constexpr int KS = QW + kMaxConvL + 8;
+    __shared__ float Ds[kMaxConvL * 32];          // [u][l - l0]
+    __shared__ float Ks[KS];                      // k'(qlo + x)
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 31, g = lane >> 5;
+    const int l0 = blockIdx.y * 32;
+    const int64_t e0 = (int64_t)blockIdx.x * QW;
+    const int64_t qlo = e0 - (L - 1);
+    const int nch = (L + 7) / 8;
+
+    stage_slice<64 * NW>(DT, L, r, l0, Ds);
+    for (int idx = tid; idx < QW + nch * 8; idx += 64 * NW) {
+        const int64_t n = qlo + idx;
+        float v = 0.0f;
+        if (n >= 0 && n < N) v = reverse ? k[N - 1 - n] : k[n];
+        Ks[idx] = v;
     }
-    *reinterpret_cast<f32x4*>(out + v * 16) = w;
+    __syncthreads();
+
+    f32x16 acc;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+    const float* kp = Ks + wave * 32 + row;        // lane's lag, tap 0
+    for (int ch = 0; ch < nch; ++ch) {
+        const float* dp = &Ds[(8 * ch + 4 * g) * 32 + row];
+        const float* hp = kp + 8 * ch + 4 * g;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[0], hp[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[32], hp[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[64], hp[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[96], hp[3], acc, 0, 0, 0);
+    }
+
+    const int64_t e = e0 + wave * 32 + row;
+    if (e >= ncp * L) return;
+    const int64_t c = e / L;
+    const int b = L - 1 - (int)(e - c * L);
+    const int64_t cb = b / 32;
+    const int bl = b % 32;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int l = l0 + 8 * (j >> 2) + 4 * g + (j & 3);
+        if (l >= r) continue;
+        const int64_t kk = (int64_t)l * ncp + c;
+        const int ln = bl + 32 * (int)((kk % 8) / 4);
+        const int64_t off = ((cb * k_nkb + kk / 8) * 64 + ln) * 16 + (kk % 4) * 4;
+        *reinterpret_cast<float*>(out + off) = acc[j];
+    }
+}
+
+// Zero fill (16-byte stores) of the packed kernel operand, needed when L is
+// not a multiple of 32 and the last row tile has padding rows b >= L.
+__global__ __launch_bounds__(256) void zero16_kernel(f32x4* __restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 }
 
 // ---- step 3: the reduced cross-correlation ------------------------------------
+// Workgroup tile: BM output rows a x BN phases b, for one contiguous range of
+// projections [l_lo, l_hi) (the split; several splits raise the number of
+// workgroups when the tiles alone do not fill the chip).  Per k-block (8
+// consecutive kernel blocks c of one projection l) the workgroup stages in
+// LDS the Hankel window sc_l[a0 + c0 .. a0 + c0 + BM + 8) and the BN x 8
+// slice of the packed kernel operand, double buffered, one barrier per
+// k-block.  A lane's A fragment is sc_l[a + c0 + 4g + e], e < 4 (rows
+// a = lane % 32 of the block, g = lane / 32), matching the packed B lanes.
 template <int WM, int WN, int WAVES_M, int WAVES_N>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
     const float* __restrict__ sc, int64_t nbp, const char* __restrict__ Kp, int64_t k_nrb, int64_t k_nkb,
-    int64_t nkb, int ncp, int L, int64_t nout, float* __restrict__ y, int64_t tiles_m, int64_t ntiles)
+    int64_t ncp, int r, int nsplit, int L, int64_t nout, float* __restrict__ y, float* __restrict__ part,
+    int64_t tiles_m)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
+    constexpr int BMB = WM * WAVES_M, BNB = WN * WAVES_N;
+    constexpr int BM = 32 * BMB;
+    constexpr int AW = BM + 8;
+    constexpr int NCH = BNB * 64;
+    constexpr int B_PER_T = (NCH + NT - 1) / NT;
+    constexpr int A_PER_T = (AW + NT - 1) / NT;
+    __shared__ __align__(16) f32x4 Bs[2][NCH];
+    __shared__ float As[2][AW];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave % WAVES_M, wn = wave / WAVES_M;
-    const int64_t tile = blockIdx.x;
-    const int64_t tm = tile % tiles_m, tn = tile / tiles_m;
-    const int64_t rb0 = (tm * WAVES_M + wm) * WM;
-    const int64_t cb0 = (tn * WAVES_N + wn) * WN;
+    const int64_t tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    const int sp = blockIdx.y;
+    const int l_lo = (int)((int64_t)r * sp / nsplit), l_hi = (int)((int64_t)r * (sp + 1) / nsplit);
+    const int64_t kpl = ncp / 8;
+    const int64_t nst = (int64_t)(l_hi - l_lo) * kpl;
+    const int64_t a0 = tm * BM;
     const int row = lane & 31, g = lane >> 5;
 
-    // Projections are visited from the highest l down to l = 0, each into a
-    // fresh partial accumulator that is then added to the total: the many
-    // small high-order products are summed among themselves before they meet
-    // the large low-order ones (blocked summation, no extra memory traffic).
+    // B chunk sources (k-block offset added per step)
+    const char* bsrc[B_PER_T];
+    bool bok[B_PER_T];
+#pragma unroll
+    for (int i = 0; i < B_PER_T; ++i) {
+        const int c = tid + i * NT;
+        const int blk = c / 64, lc = c % 64;
+        const int64_t cb = tn * BNB + blk;
+        bok[i] = c < NCH && cb < k_nrb;
+        bsrc[i] = Kp + ((bok[i] ? cb : 0) * k_nkb * 64 + lc) * 16;
+    }
+    f32x4 bst[B_PER_T];
+    float ast[A_PER_T];
+    // step st: projection l = l_hi - 1 - st / kpl (highest first), kernel blocks c0 = 8 (st % kpl)
+    auto gload = [&](int64_t st) {
+        const int64_t l = l_hi - 1 - st / kpl;
+        const int64_t cblk = st % kpl;
+        const int64_t kb = l * kpl + cblk;
+        const float* ap = sc + l * nbp + a0 + cblk * 8;
+#pragma unroll
+        for (int i = 0; i < A_PER_T; ++i) {
+            const int x = tid + i * NT;
+            ast[i] = x < AW ? ap[x] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < B_PER_T; ++i)
+            bst[i] = bok[i] ? *reinterpret_cast<const f32x4*>(bsrc[i] + kb * 1024) : f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+    auto swrite = [&](int s) {
+#pragma unroll
+        for (int i = 0; i < A_PER_T; ++i) {
+            const int x = tid + i * NT;
+            if (x < AW) As[s][x] = ast[i];
+        }
+#pragma unroll
+        for (int i = 0; i < B_PER_T; ++i) {
+            const int c = tid + i * NT;
+            if (c < NCH) Bs[s][c] = bst[i];
+        }
+    };
+
+    // Each projection's products are summed in a fresh accumulator and then
+    // added to the total, highest projection first: the many small high-order
+    // terms meet the large low-order ones only as one partial sum each.
     f32x16 tot[WM][WN], acc[WM][WN];
 #pragma unroll
     for (int a = 0; a < WM; ++a)
@@ -131,47 +285,30 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
 #pragma unroll
             for (int j = 0; j < 16; ++j) tot[a][b][j] = acc[a][b][j] = 0.0f;
 
-    const char* kp[WN];
-    bool kv[WN];
-#pragma unroll
-    for (int b = 0; b < WN; ++b) {
-        kv[b] = cb0 + b < k_nrb;
-        kp[b] = Kp + ((kv[b] ? cb0 + b : 0) * k_nkb * 64 + lane) * 16;
+    if (nst > 0) {
+        gload(0);
+        swrite(0);
     }
-
-    // k-block visited at step s: projection r-1 - s / kpl, block s % kpl
-    const int64_t kpl = ncp / 8;
-    const int64_t r = nkb / kpl;
-    auto kb_of = [&](int64_t st) { return (r - 1 - st / kpl) * kpl + st % kpl; };
-
-    auto load = [&](int64_t kb, f32x4 (&xf)[WM], f32x4 (&yf)[WN]) {
-        const int64_t kk = kb * 8;
-        const int64_t l = kk / ncp;
-        const int64_t c0 = kk - l * ncp;
-        const float* base = sc + l * nbp + c0 + 4 * g + row;
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        const int s = (int)(st & 1);
+        if (st + 1 < nst) gload(st + 1);
+        f32x4 xf[WM], yf[WN];
 #pragma unroll
         for (int a = 0; a < WM; ++a) {
-            const float* p = base + (rb0 + a) * 32;
+            const float* p = &As[s][(wm * WM + a) * 32 + row + 4 * g];
             xf[a] = f32x4{p[0], p[1], p[2], p[3]};
         }
 #pragma unroll
-        for (int b = 0; b < WN; ++b)
-            yf[b] = kv[b] ? *reinterpret_cast<const f32x4*>(kp[b] + kb * 1024) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    };
-
-    f32x4 xc[WM], yc[WN];
-    if (nkb > 0) load(kb_of(0), xc, yc);
-    for (int64_t st = 0; st < nkb; ++st) {
-        f32x4 xn[WM], yn[WN];
-        if (st + 1 < nkb) load(kb_of(st + 1), xn, yn);
+        for (int b = 0; b < WN; ++b) yf[b] = Bs[s][(wn * WN + b) * 64 + lane];
 #pragma unroll
         for (int a = 0; a < WM; ++a)
 #pragma unroll
             for (int b = 0; b < WN; ++b) {
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xc[a][0], yc[b][0], acc[a][b], 0, 0, 0);
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xc[a][1], yc[b][1], acc[a][b], 0, 0, 0);
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xc[a][2], yc[b][2], acc[a][b], 0, 0, 0);
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xc[a][3], yc[b][3], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[a][0], yf[b][0], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[a][1], yf[b][1], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[a][2], yf[b][2], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[a][3], yf[b][3], acc[a][b], 0, 0, 0);
             }
         if (st % kpl == kpl - 1) {
 #pragma unroll
@@ -184,29 +321,40 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
                         acc[a][b][j] = 0.0f;
                     }
         }
-        if (st + 1 < nkb) {
-#pragma unroll
-            for (int a = 0; a < WM; ++a) xc[a] = xn[a];
-#pragma unroll
-            for (int b = 0; b < WN; ++b) yc[b] = yn[b];
-        }
+        if (st + 1 < nst) swrite(s ^ 1);
+        __syncthreads();
     }
 
+    float* dst = nsplit == 1 ? y : part + (int64_t)sp * nout;
 #pragma unroll
     for (int a = 0; a < WM; ++a)
 #pragma unroll
         for (int b = 0; b < WN; ++b)
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const int64_t ar = (rb0 + a) * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-                const int64_t bc = (cb0 + b) * 32 + (lane & 31);
+                const int64_t ar = a0 + (wm * WM + a) * 32 + 8 * (j >> 2) + 4 * g + (j & 3);
+                const int64_t bc = (tn * BNB + wn * WN + b) * 32 + row;
                 const int64_t m = ar * L + bc;
-                if (bc < L && m < nout) y[m] = tot[a][b][j];
+                if (bc < L && m < nout) dst[m] = tot[a][b][j];
             }
 }
 
-constexpr int XW_M = 2, XW_N = 2, XWAVES_M = 2, XWAVES_N = 2;
+// Sum of the split partials, highest projection range first.
+__global__ __launch_bounds__(256) void split_sum_kernel(const float* __restrict__ part, int nsplit, int64_t nout,
+                                                        float* __restrict__ y)
+{
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= nout) return;
+    float v = part[(int64_t)(nsplit - 1) * nout + m];
+    for (int s = nsplit - 2; s >= 0; --s) v += part[(int64_t)s * nout + m];
+    y[m] = v;
+}
+
+// tile shapes: 128 x 256 (8 waves) when L > 128, else 128 x 128 (4 waves)
+constexpr int XW_M = 2, XW_N = 2, XWAVES_M = 2;
 constexpr int XBM = 32 * XW_M * XWAVES_M;
+constexpr int kXcorrTargetWG = 512;    // workgroups to aim for with splits
+constexpr int kXcorrMinSteps = 64;     // fewest k-blocks per split
 
 }  // namespace
 
@@ -222,9 +370,17 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
     g.nbp = rup(g.tiles_m * XBM + g.ncp, 64);       // projected-signal row length
     g.k_nrb = cdiv(L, 32);
     g.k_nkb = (int64_t)r * g.ncp / 8;
+    const int bnb = L > 128 ? 8 : 4;
+    g.tiles_n = cdiv(g.k_nrb, bnb);
+    const int64_t tiles = g.tiles_m * g.tiles_n;
+    int64_t ns = std::max<int64_t>(1, kXcorrTargetWG / std::max<int64_t>(1, tiles));
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, g.k_nkb / kXcorrMinSteps));
+    ns = std::min<int64_t>(ns, r);
+    g.nsplit = (int)ns;
     g.sc_bytes = rup((int64_t)r * g.nbp * 4, 256);
     g.k_bytes = g.k_nrb * g.k_nkb * 1024;
-    g.total = g.sc_bytes + g.k_bytes;
+    g.part_bytes = g.nsplit > 1 ? rup((int64_t)g.nsplit * g.nout * 4, 256) : 0;
+    g.total = g.sc_bytes + g.k_bytes + g.part_bytes;
     return g;
 }
 
@@ -235,38 +391,43 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
     char* kp = (char*)a.ws + g.sc_bytes;
     // step 1
     {
-        int LR = 1;
-        while (LR < a.r) LR *= 2;
-        const int BG = 256 / LR;
-        const int bpt = (int)cdiv(kSigBlocks, BG);
-        dim3 grid((unsigned)cdiv(g.nbp, kSigBlocks));
-        const size_t lds = (size_t)kSigBlocks * (a.L + 1) * sizeof(float);
-#define SIG_LAUNCH(B)                                                                                        \
-    hipLaunchKernelGGL(sig_project_kernel<B>, grid, dim3(256), lds, st, a.s, a.W, a.L, a.r, LR, a.C, sc, g.nbp)
-        if (bpt <= 1) SIG_LAUNCH(1);
-        else if (bpt <= 2) SIG_LAUNCH(2);
-        else if (bpt <= 4) SIG_LAUNCH(4);
-        else if (bpt <= 8) SIG_LAUNCH(8);
-        else if (bpt <= 16) SIG_LAUNCH(16);
-        else SIG_LAUNCH(32);
-#undef SIG_LAUNCH
+        if (a.L > kMaxConvL) return -2;
+        dim3 grid((unsigned)cdiv(g.nbp, 128), (unsigned)cdiv(a.r, 32));
+        const bool vec = a.L % 4 == 0 && ((uintptr_t)a.s % 16) == 0;
+        if (vec)
+            hipLaunchKernelGGL((sig_project_kernel<4, true>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, g.nbp);
+        else
+            hipLaunchKernelGGL((sig_project_kernel<4, false>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, g.nbp);
         if (hipGetLastError() != hipSuccess) return -1;
     }
     // step 2
     {
-        const int64_t lanes = g.k_nrb * g.k_nkb * 64;
-        hipLaunchKernelGGL(kmat_pack_kernel, dim3((unsigned)cdiv(lanes, 256)), dim3(256), 0, st, a.k, (int)a.N,
-                           a.reverse, a.L, a.r, (int)g.ncp, a.DT, kp, g.k_nrb, g.k_nkb);
+        if (a.L % 32 != 0) {
+            const int64_t n16 = g.k_nrb * g.k_nkb * 64;
+            hipLaunchKernelGGL(zero16_kernel, dim3((unsigned)cdiv(n16, 256)), dim3(256), 0, st, (f32x4*)kp, n16);
+            if (hipGetLastError() != hipSuccess) return -1;
+        }
+        dim3 grid((unsigned)cdiv(g.ncp * a.L, 128), (unsigned)cdiv(a.r, 32));
+        hipLaunchKernelGGL(kphase_kernel<4>, grid, dim3(256), 0, st, a.k, a.N, a.reverse, a.L, a.r, g.ncp, a.DT, kp,
+                           g.k_nkb);
         if (hipGetLastError() != hipSuccess) return -1;
     }
     // step 3
     {
-        const int64_t tiles_n = cdiv(g.k_nrb, (int64_t)XWAVES_N * XW_N);
-        const int64_t ntiles = g.tiles_m * tiles_n;
-        hipLaunchKernelGGL((xcorr_kernel<XW_M, XW_N, XWAVES_M, XWAVES_N>), dim3((unsigned)ntiles),
-                           dim3(64 * XWAVES_M * XWAVES_N), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb, g.k_nkb,
-                           (int)g.ncp, a.L, g.nout, a.y, g.tiles_m, ntiles);
+        float* part = (float*)((char*)a.ws + g.sc_bytes + g.k_bytes);
+        dim3 grid((unsigned)(g.tiles_m * g.tiles_n), (unsigned)g.nsplit);
+        if (a.L > 128)
+            hipLaunchKernelGGL((xcorr_kernel<XW_M, XW_N, XWAVES_M, 4>), grid, dim3(64 * XWAVES_M * 4), 0, st, sc, g.nbp,
+                               kp, g.k_nrb, g.k_nkb, g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
+        else
+            hipLaunchKernelGGL((xcorr_kernel<XW_M, XW_N, XWAVES_M, 2>), grid, dim3(64 * XWAVES_M * 2), 0, st, sc, g.nbp,
+                               kp, g.k_nrb, g.k_nkb, g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
         if (hipGetLastError() != hipSuccess) return -1;
+        if (g.nsplit > 1) {
+            hipLaunchKernelGGL(split_sum_kernel, dim3((unsigned)cdiv(g.nout, 256)), dim3(256), 0, st, part, g.nsplit,
+                               g.nout, a.y);
+            if (hipGetLastError() != hipSuccess) return -1;
+        }
     }
     return 0;
 }

@@ -23,7 +23,7 @@ template <int PREC> struct MT;
 
 // Plain 16-byte lane vectors.
 template <typename F>
-__device__ inline F load_plain(const char* plane, int64_t plane_bytes, int64_t tile, int lane)
+__device__ __forceinline__ F load_plain(const char* plane, int64_t plane_bytes, int64_t tile, int lane)
 {
     (void)plane_bytes;
     return *reinterpret_cast<const F*>(plane + (tile * 64 + lane) * 16);
@@ -34,8 +34,8 @@ template <> struct MT<P_F32> {
     using frag = f32x4;
     using acc = f32x16;
     using out_t = float;
-    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
-    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    __device__ __forceinline__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
+    __device__ __forceinline__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][0], b[0][0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][1], b[0][1], c, 0, 0, 0);
@@ -49,8 +49,8 @@ template <> struct MT<P_F64> {
     using frag = f64x2;
     using acc = f64x4;
     using out_t = double;
-    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
-    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    __device__ __forceinline__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
+    __device__ __forceinline__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0][0], b[0][0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0][1], b[0][1], c, 0, 0, 0);
@@ -62,8 +62,8 @@ template <> struct MT<P_BF16> {
     using frag = bf16x8;
     using acc = f32x16;
     using out_t = float;
-    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
-    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    __device__ __forceinline__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
+    __device__ __forceinline__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], c, 0, 0, 0);
     }
@@ -74,8 +74,8 @@ template <> struct MT<P_BF16X3> {
     using frag = bf16x8;
     using acc = f32x16;
     using out_t = float;
-    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
-    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    __device__ __forceinline__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
+    __device__ __forceinline__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], c, 0, 0, 0);
@@ -88,8 +88,8 @@ template <> struct MT<P_F16> {
     using frag = f16x8;
     using acc = f32x16;
     using out_t = float;
-    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
-    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    __device__ __forceinline__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
+    __device__ __forceinline__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[0], b[0], c, 0, 0, 0);
     }
@@ -100,8 +100,8 @@ template <> struct MT<P_F16X3> {
     using frag = f16x8;
     using acc = f32x16;
     using out_t = float;
-    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
-    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    __device__ __forceinline__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_plain<frag>(pl, pb, t, lane); }
+    __device__ __forceinline__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[1], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[0], b[1], c, 0, 0, 0);
@@ -117,7 +117,7 @@ struct Fp8Frag {
     int s;
 };
 
-__device__ inline Fp8Frag load_fp8(const char* plane, int64_t plane_bytes, int64_t tile, int lane)
+__device__ __forceinline__ Fp8Frag load_fp8(const char* plane, int64_t plane_bytes, int64_t tile, int lane)
 {
     Fp8Frag f;
     f.v = *reinterpret_cast<const i32x8*>(plane + (tile * 64 + lane) * 32);
@@ -130,8 +130,8 @@ template <> struct MT<P_FP8> {
     using frag = Fp8Frag;
     using acc = f32x16;
     using out_t = float;
-    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_fp8(pl, pb, t, lane); }
-    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    __device__ __forceinline__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_fp8(pl, pb, t, lane); }
+    __device__ __forceinline__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[0].v, b[0].v, c, 0, 0, 0, a[0].s, 0, b[0].s);
     }
@@ -142,8 +142,8 @@ template <> struct MT<P_FP8X2> {
     using frag = Fp8Frag;
     using acc = f32x16;
     using out_t = float;
-    __device__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_fp8(pl, pb, t, lane); }
-    __device__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
+    __device__ __forceinline__ static frag load(const char* pl, int64_t pb, int64_t t, int lane) { return load_fp8(pl, pb, t, lane); }
+    __device__ __forceinline__ static void mma(acc& c, const frag (&a)[PLANES], const frag (&b)[PLANES])
     {
         c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[1].v, b[0].v, c, 0, 0, 0, a[1].s, 0, b[0].s);
         c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[0].v, b[1].v, c, 0, 0, 0, a[0].s, 0, b[1].s);
@@ -153,7 +153,7 @@ template <> struct MT<P_FP8X2> {
 
 // Output position of accumulator element j of `lane` within an RB x RB block.
 template <int RB>
-__device__ inline void acc_pos(int j, int lane, int& row, int& col)
+__device__ __forceinline__ void acc_pos(int j, int lane, int& row, int& col)
 {
     if constexpr (RB == 32) {
         row = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
@@ -167,7 +167,7 @@ __device__ inline void acc_pos(int j, int lane, int& row, int& col)
 // XCD-aware remap of the hardware workgroup id: the dispatcher hands
 // workgroup b to XCD b % 8, so logical tiles [x*n/8, (x+1)*n/8) all run on
 // XCD x and share its L2.
-__device__ inline int64_t xcd_remap(int64_t b, int64_t n)
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n)
 {
     const int64_t x = b % 8, i = b / 8;
     const int64_t q = n / 8, rem = n % 8;
@@ -177,7 +177,7 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t n)
 // One workgroup tile (tm, tn) of R = X Y^T: the body shared by the single
 // and the grouped (persistent) launches.
 template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
-__device__ inline void gemm_tile(
+__device__ __forceinline__ void gemm_tile(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
     int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
@@ -279,7 +279,7 @@ __device__ inline void gemm_tile(
 // workgroup instead of once per wave, and the global loads of k-block k+1
 // overlap the MFMAs of k-block k.  16-byte lane formats only (not FP8).
 template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
-__device__ inline void gemm_tile_lds(
+__device__ __forceinline__ void gemm_tile_lds(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
     int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
@@ -399,7 +399,7 @@ __device__ inline void gemm_tile_lds(
 
 // Kernel body selector: KIND 0 = direct fragment loads, 1 = LDS-staged.
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
-__device__ inline void gemm_any(
+__device__ __forceinline__ void gemm_any(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
     int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
@@ -422,7 +422,12 @@ constexpr size_t gemm_lds_bytes()
 }
 
 // OCC = minimum resident workgroups per CU the register allocation must allow.
-#define PJ_GEMM_BOUNDS __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
+// The two-plane FP8 fragments (two 32-byte planes plus scales, double
+// buffered) do not fit the 256 registers per lane of two resident waves per
+// SIMD, so that format always gets the whole register file.
+template <int PREC, int OCC>
+constexpr int gemm_occ() { return PREC == P_FP8X2 ? 1 : OCC; }
+#define PJ_GEMM_BOUNDS __launch_bounds__(64 * WAVES_M * WAVES_N, (gemm_occ<PREC, OCC>()))
 
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
 __global__ PJ_GEMM_BOUNDS void gemm_kernel(
@@ -563,14 +568,14 @@ int gemm_config_tile(int prec, int cfg, int* tile_m, int* tile_n)
 int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
 {
     (void)nkb;
-    if (prec == P_F64) return 3;
     // small problems: smaller tiles so that the grid still covers the chip
     const int64_t tiles128 = cdiv(P, 128) * cdiv(Q, 128);
     if (tiles128 < 256) return 5;
-    if (prec == P_FP8 || prec == P_FP8X2) return 0;
-    if (prec == P_F32) return 6;                                   // LDS 128 x 128
-    if (prec == P_BF16X3 || prec == P_F16X3) return 9;             // LDS 128 x 256, 8 waves
-    return 6;
+    if (prec == P_F64) return 10;                                  // LDS, 8 waves, 128 x 64 (16 x 16 blocks)
+    if (prec == P_FP8) return 0;
+    if (prec == P_FP8X2) return 5;
+    if (prec == P_BF16X3 || prec == P_F16X3) return 10;            // LDS 256 x 128, 8 waves
+    return 6;                                                      // LDS 128 x 128
 }
 
 int launch_gemm(int prec, const GemmArgs& a, int cfg, hipStream_t s)

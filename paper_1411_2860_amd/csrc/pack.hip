@@ -49,7 +49,7 @@ struct PackJob {
 
 // ---- OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits,
 // largest finite 448, no infinities) with round-to-nearest-even; |v| <= 448.
-__device__ inline unsigned fp8_e4m3_rne(float v)
+__device__ __forceinline__ unsigned fp8_e4m3_rne(float v)
 {
     const unsigned sign = (__float_as_uint(v) >> 24) & 0x80u;
     const float a = fabsf(v);
@@ -67,7 +67,7 @@ __device__ inline unsigned fp8_e4m3_rne(float v)
 // ---- conversion of E accumulated values into one lane vector -------------
 
 template <int PREC, int E, typename TIn>
-__device__ inline void store_lane(char* __restrict__ out, int64_t off, int64_t plane_stride, int64_t plane_bytes,
+__device__ __forceinline__ void store_lane(char* __restrict__ out, int64_t off, int64_t plane_stride, int64_t plane_bytes,
                                   const TIn (&v)[E])
 {
     if constexpr (PREC == P_F64) {
@@ -122,7 +122,7 @@ template <int PREC> struct Cmap {
     static constexpr int TRc = 64 / NGc;
 };
 
-__device__ inline unsigned fp8_exp_byte(float amax, float& inv, float& sc)
+__device__ __forceinline__ unsigned fp8_exp_byte(float amax, float& inv, float& sc)
 {
     int ex = -127;
     if (amax > 0.0f) {
@@ -136,7 +136,7 @@ __device__ inline unsigned fp8_exp_byte(float amax, float& inv, float& sc)
     return (unsigned)(ex + 127);
 }
 
-__device__ inline float fp8_decode(unsigned c)
+__device__ __forceinline__ float fp8_decode(unsigned c)
 {
     const unsigned mag = c & 0x7Fu;
     const float val = (mag < 8u) ? (float)mag * 0.001953125f
@@ -146,7 +146,7 @@ __device__ inline float fp8_decode(unsigned c)
 
 // 8 values of one MX block quarter: codes (2 words) with the block's scale;
 // optionally the dequantised values.
-__device__ inline void fp8_encode8(const float* v, float inv, float sc, unsigned& w0, unsigned& w1, float* deq)
+__device__ __forceinline__ void fp8_encode8(const float* v, float inv, float sc, unsigned& w0, unsigned& w1, float* deq)
 {
     w0 = w1 = 0;
 #pragma unroll
@@ -159,7 +159,7 @@ __device__ inline void fp8_encode8(const float* v, float inv, float sc, unsigned
     }
 }
 
-__device__ inline float quad_max(float a)
+__device__ __forceinline__ float quad_max(float a)
 {
     a = fmaxf(a, __shfl_xor(a, 1));
     a = fmaxf(a, __shfl_xor(a, 2));
@@ -171,7 +171,7 @@ __device__ inline float quad_max(float a)
 // g / 4.  The instruction reads block h of row `row` as bytes 16h..16h+15 of
 // lane row (indices 32h..32h+15) and of lane 32 + row (32h+16..32h+31).
 template <int PREC>
-__device__ inline void store_fp8_quarter(char* __restrict__ out, int64_t tile, int rib, int g, int64_t plane_stride,
+__device__ __forceinline__ void store_fp8_quarter(char* __restrict__ out, int64_t tile, int rib, int g, int64_t plane_stride,
                                          int64_t plane_bytes, const float (&v)[8])
 {
     const int h = g / 4, sub = g % 4;
@@ -205,7 +205,7 @@ __device__ inline void store_fp8_quarter(char* __restrict__ out, int64_t tile, i
 }
 
 template <typename TIn, int PREC, int RL, int NCH>
-__device__ inline void pack_tile(const PackJob<TIn>& J, int64_t tix)
+__device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 {
     constexpr Layout ly = layout_of(PREC);
     constexpr int KB = ly.KB, RB = ly.RB;

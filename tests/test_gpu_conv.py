@@ -121,3 +121,16 @@ def test_full_size_sampled(pg, long_signal, N, r):
     if r == 256:
         exact = np.array([np.dot(k, s[m:m + N]) for m in ms])
         assert oracle.rel_fro(got, exact) < 1e-5
+
+
+@pytest.mark.parametrize("W,N,L,r", [
+    (65536, 4096, 64, 20),      # two projection ranges
+    (65536, 4096, 64, 64),      # nine uneven ranges over 64 projections
+    (1 << 18, 8192, 256, 64),   # five ranges, 256-phase tiles
+])
+def test_split_contraction_every_output(pg, W, N, L, r):
+    """Long contractions are cut into contiguous projection ranges that run
+    as separate workgroups and are summed afterwards; every output checked."""
+    s = inputs.ar2_signal(W, seed=27)
+    k, _ = inputs.excerpt_kernel(s, N, seed=28)
+    _check(pg, s, k, "dct2", L, r)
