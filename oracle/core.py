@@ -27,7 +27,7 @@ __all__ = [
     "project_a", "project_b", "gemm_proj", "gemm_proj_block", "gemm_proj_grad",
     "gemm_proj_closed", "gemm_proj_brute", "q_matrix", "blockdiag", "gemm_proj_grad_block",
     "project_signal", "project_kernel", "xcorr_proj", "xcorr_proj_at",
-    "xcorr_proj_closed", "xcorr_proj_sliding",
+    "xcorr_proj_closed", "xcorr_proj_sliding", "xcorr_proj_block_rate",
     "rel_fro", "snr_db", "work_gemm_plain", "work_gemm_proj",
     "work_conv_plain_time", "work_conv_proj_time",
 ]
@@ -401,6 +401,27 @@ def xcorr_proj_sliding(s, k, C, D, r: int) -> np.ndarray:
     kt = (kp.reshape(nb, L) @ q_matrix(C, D, r).T).reshape(-1)
     sp = np.zeros(s.size + nb * L - k.size); sp[:s.size] = s
     return np.correlate(sp, kt, mode="valid")[: s.size - k.size + 1]
+
+
+def xcorr_proj_block_rate(s, k, C, D, r: int) -> np.ndarray:
+    """Block-rate projected valid cross-correlation (Sec. III-A: results may be
+    omitted and interpolated from their neighbours; Sec. IV-A: one projection
+    at half the sampling rate for L = 2).  Only the outputs m = aL are computed
+    -- aligned signal blocks against aligned kernel blocks, i.e. the projected
+    cross-correlation at those positions.  An output aL + f (0 < f < L) lying
+    before the next computed output is the linear interpolation
+    y[aL] + (f / L) (y[(a+1)L] - y[aL]) (for L = 2 the average of the two
+    neighbours); past the last computed output its value is held."""
+    s, k = _f64(s), _f64(k)
+    L = _f64(C).shape[0]
+    nout = s.size - k.size + 1
+    nd = (nout - 1) // L + 1
+    yd = xcorr_proj_at(s, k, C, D, r, np.arange(nd, dtype=np.int64) * L)
+    m = np.arange(nout)
+    a, f = m // L, m % L
+    nxt = np.minimum(a + 1, nd - 1)
+    y = yd[a] + (f / L) * (yd[nxt] - yd[a])
+    return np.where(a + 1 < nd, y, yd[a])
 
 
 # -------------------------------------------------------- metrics and counts

@@ -113,3 +113,58 @@ def test_error_decreases_on_ar2_signal():
     errs = [oracle.rel_fro(oracle.xcorr_proj(s, k, C, D, r), ref) for r in (1, 2, 4, 8, 16)]
     assert all(b < a for a, b in zip(errs, errs[1:]))
     assert errs[-1] < 1e-12
+
+
+# ---- block rate (outputs at m = aL, the rest interpolated) ----------------------
+
+@pytest.mark.parametrize("kind,L", [("haar", 2), ("haar", 4), ("dct2", 4), ("dct2", 8)])
+@pytest.mark.parametrize("W,N", [(103, 17), (96, 32), (40, 40), (61, 1)])
+def test_block_rate_exact_for_affine_output(kind, L, W, N):
+    """An affine signal s[n] = alpha n + beta makes the exact cross-correlation
+    affine in m; at r = L the computed samples are exact, so the linear
+    interpolation between them must reproduce the exact output everywhere
+    before the last computed sample, and hold that sample's value after it."""
+    C, D = oracle.basis(kind, L)
+    s = 0.37 * np.arange(W) - 5.0
+    k = _rand(N, 7)
+    exact = np.correlate(s, k, mode="valid")
+    y = oracle.xcorr_proj_block_rate(s, k, C, D, L)
+    nout = W - N + 1
+    last = ((nout - 1) // L) * L
+    np.testing.assert_allclose(y[:last + 1], exact[:last + 1], rtol=1e-10, atol=1e-9)
+    np.testing.assert_allclose(y[last:], np.full(nout - last, exact[last]), rtol=1e-10, atol=1e-9)
+
+
+@pytest.mark.parametrize("kind,L", [("haar", 2), ("dct2", 4), ("dct2", 16)])
+@pytest.mark.parametrize("r", [1, 2])
+def test_block_rate_samples_are_the_closed_form(kind, L, r):
+    """The computed samples m = aL equal the exact cross-correlation of the
+    block-projected signal (an independent route, numpy.correlate) there."""
+    C, D = oracle.basis(kind, L)
+    s, k = _rand(301, 8), _rand(45, 9)
+    y = oracle.xcorr_proj_block_rate(s, k, C, D, r)
+    closed = oracle.xcorr_proj_closed(s, k, C, D, r)
+    np.testing.assert_allclose(y[::L], closed[::L], rtol=1e-10, atol=1e-10)
+
+
+def test_block_rate_with_unit_blocks_is_every_output():
+    """L = 1: every output is a computed sample, no interpolation."""
+    C, D = oracle.basis("identity", 1)
+    s, k = _rand(77, 10), _rand(9, 11)
+    np.testing.assert_allclose(oracle.xcorr_proj_block_rate(s, k, C, D, 1), np.correlate(s, k, "valid"),
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_block_rate_half_samples_error_is_interpolation_error():
+    """L = 2, r = 2 (exact samples): the only error left is the interpolation
+    of the odd outputs, which vanishes on the even ones and is bounded by the
+    second difference of the exact output on the odd ones."""
+    C, D = oracle.basis("haar", 2)
+    s = inputs.ar2_signal(4000, seed=12, burn=512)
+    k, _ = inputs.excerpt_kernel(s, 200, seed=13)
+    exact = np.correlate(s, k, "valid")
+    y = oracle.xcorr_proj_block_rate(s, k, C, D, 2)
+    np.testing.assert_allclose(y[::2], exact[::2], rtol=1e-9, atol=1e-9)
+    odd = np.arange(1, exact.size - 1, 2)
+    second = np.abs(exact[odd - 1] - 2 * exact[odd] + exact[odd + 1]) / 2
+    assert np.all(np.abs(y[odd] - exact[odd]) <= second + 1e-9)
