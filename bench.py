@@ -269,7 +269,7 @@ def main():
         bc = pg.Basis("dct2", Lc)
         Cc, Dc = bc.matrices()
         ident = pg.Basis("identity", 32)
-        res = []
+        res = {"full_rate": [], "block_rate": [], "paper_points": []}
         for N in (1024, 4096, 16384):
             k, o = inputs.excerpt_kernel(s, N, seed=inputs.SEED_KERNEL)
             kd = torch.from_numpy(k.astype(np.float32)).to(dev)
@@ -279,19 +279,49 @@ def main():
             ms = np.unique(np.concatenate([[0, nout - 1, o], ms_rng.integers(0, nout, 61)]))
             exact = np.array([np.dot(k, s[m:m + N]) for m in ms])
             flops = 2.0 * nout * N
-            for rr, b, lab in [(1, bc, "dct2"), (16, bc, "dct2"), (64, bc, "dct2"), (256, bc, "dct2"),
-                               (32, ident, "plain")]:
-                ws = torch.empty(pg.conv1d_workspace_bytes(Wc, N, b.L, rr), dtype=torch.uint8, device=dev)
-                fn = lambda: pg.conv1d(sd, kd, rr, b, out=y, workspace=ws)
+            runs = [(1, bc, "dct2", "full"), (16, bc, "dct2", "full"), (64, bc, "dct2", "full"),
+                    (256, bc, "dct2", "full"), (32, ident, "plain", "full")]
+            if N == 16384:
+                runs += [(16, bc, "dct2", "block"), (64, bc, "dct2", "block"), (256, bc, "dct2", "block")]
+            for rr, b, lab, rate in runs:
+                ws = torch.empty(pg.conv1d_workspace_bytes(Wc, N, b.L, rr, rate=rate), dtype=torch.uint8, device=dev)
+                fn = lambda: pg.conv1d(sd, kd, rr, b, out=y, workspace=ws, rate=rate)
                 t = autotune._time_ms(fn, 10, warmup=3)
                 got = y[torch.from_numpy(ms).to(dev)].double().cpu().numpy()
-                ent = {"N": N, "basis": lab, "L": b.L, "r": rr, "ms": round(t, 5),
+                ent = {"N": N, "basis": lab, "L": b.L, "r": rr, "rate": rate, "ms": round(t, 5),
                        "exact_equiv_tflops": round(flops / (t * 1e-3) / 1e12, 3),
                        "rel_err_vs_fp64_exact": f3(oracle.rel_fro(got, exact))}
                 if lab == "dct2":
-                    proj = oracle.xcorr_proj_at(s, k, Cc, Dc, rr, ms)
+                    if rate == "full":
+                        proj = oracle.xcorr_proj_at(s, k, Cc, Dc, rr, ms)
+                    else:
+                        proj = oracle.xcorr_proj_block_rate_at(s, k, Cc, Dc, rr, ms)
                     ent["rel_err_vs_fp64_projected"] = f3(oracle.rel_fro(got, proj))
-                res.append(ent)
+                res["full_rate" if rate == "full" else "block_rate"].append(ent)
+                del ws
+        # the paper's CONV operating points: a block of 20000 samples, kernels
+        # of 600 and 1200 samples, L = 2 Haar, one projection at half or full
+        # sampling rate, and the exact result (both projections) for reference
+        s20 = inputs.ar2_signal(20000, seed=inputs.SEED_AR2)
+        s20d = torch.from_numpy(s20.astype(np.float32)).to(dev)
+        h2 = pg.Basis("haar", 2)
+        for N in (600, 1200):
+            k20, _ = inputs.excerpt_kernel(s20, N, seed=inputs.SEED_KERNEL)
+            k20d = torch.from_numpy(k20.astype(np.float32)).to(dev)
+            exact = np.correlate(s20, k20, "valid")
+            nout = exact.size
+            y = torch.empty(nout, dtype=torch.float32, device=dev)
+            for rr, rate, lab in [(1, "block", "1 projection, half samples"), (1, "full", "1 projection, all samples"),
+                                  (2, "full", "all projections (exact)")]:
+                ws = torch.empty(pg.conv1d_workspace_bytes(20000, N, 2, rr, rate=rate), dtype=torch.uint8,
+                                 device=dev)
+                fn = lambda: pg.conv1d(s20d, k20d, rr, h2, out=y, workspace=ws, rate=rate)
+                t = autotune._time_ms(fn, 50, warmup=5)
+                got = y.double().cpu().numpy()
+                res["paper_points"].append({"W": 20000, "N": N, "L": 2, "basis": "haar", "r": rr, "rate": rate,
+                                            "label": lab, "ms": round(t, 5),
+                                            "msamples_per_s": round(nout / (t * 1e-3) / 1e6, 2),
+                                            "snr_db_vs_fp64_exact": round(oracle.snr_db(exact, got), 2)})
                 del ws
         return res
 

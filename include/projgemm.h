@@ -73,6 +73,9 @@ typedef enum {
 } pj_precision;
 
 typedef enum { PJ_XCORR = 0, PJ_CONV = 1 } pj_conv_mode;
+/* Output rate of proj_conv1d_rate: every output, or only the outputs at the
+ * aligned lags m = aL with the others interpolated. */
+typedef enum { PJ_RATE_FULL = 0, PJ_RATE_BLOCK = 1 } pj_conv_rate;
 
 typedef struct pj_basis_s* pj_basis;
 
@@ -241,6 +244,28 @@ size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec);
  * Requires ws_bytes >= pj_conv1d_workspace_bytes(...). */
 int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k,
                 float* y, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace proj_conv1d_rate needs for the given rate (0 for
+ * invalid arguments).  For PJ_RATE_FULL this is pj_conv1d_workspace_bytes. */
+size_t pj_conv1d_rate_workspace_bytes(int64_t W, int N, int L, int r, int rate, int prec);
+
+/* proj_conv1d with a choice of output rate (paper Sec. III-A: results may be
+ * omitted and interpolated from the neighbouring ones; Sec. IV-A: one
+ * projection at half the sampling rate with L = 2, interpolating the missing
+ * samples):
+ *   PJ_RATE_FULL : every output, exactly as proj_conv1d.
+ *   PJ_RATE_BLOCK: only the outputs m = aL (a = 0 .. (W - N) / L) are
+ *     computed -- the aligned signal blocks projected with C against the
+ *     aligned kernel blocks projected with D, summed over the first r
+ *     projections (the same values proj_conv1d gives there).  An output
+ *     aL + f, 0 < f < L, with a next computed output (a+1)L <= W - N is the
+ *     linear interpolation y[aL] + (f / L) (y[(a+1)L] - y[aL]) (for L = 2 the
+ *     average of its two neighbours); past the last computed output the value
+ *     of that output is held.  The work is about 1/L of the full rate.
+ * Same arguments, errors and ownership as proj_conv1d; rate outside the enum
+ * gives PJ_ERR_ARG.  Requires ws_bytes >= pj_conv1d_rate_workspace_bytes(...). */
+int proj_conv1d_rate(pj_basis b, int r, int mode, int rate, int64_t W, const float* s, int N, const float* k,
+                     float* y, int prec, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

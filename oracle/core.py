@@ -27,7 +27,7 @@ __all__ = [
     "project_a", "project_b", "gemm_proj", "gemm_proj_block", "gemm_proj_grad",
     "gemm_proj_closed", "gemm_proj_brute", "q_matrix", "blockdiag", "gemm_proj_grad_block",
     "project_signal", "project_kernel", "xcorr_proj", "xcorr_proj_at",
-    "xcorr_proj_closed", "xcorr_proj_sliding", "xcorr_proj_block_rate",
+    "xcorr_proj_closed", "xcorr_proj_sliding", "xcorr_proj_block_rate", "xcorr_proj_block_rate_at",
     "rel_fro", "snr_db", "work_gemm_plain", "work_gemm_proj",
     "work_conv_plain_time", "work_conv_proj_time",
 ]
@@ -403,6 +403,16 @@ def xcorr_proj_sliding(s, k, C, D, r: int) -> np.ndarray:
     return np.correlate(sp, kt, mode="valid")[: s.size - k.size + 1]
 
 
+def _interpolate_block_rate(yd, m, L: int) -> np.ndarray:
+    """Outputs at positions m from the computed samples yd[a] = y[aL]: exact
+    at m = aL, linear between two computed samples, held after the last."""
+    nd = yd.size
+    a, f = m // L, m % L
+    nxt = np.minimum(a + 1, nd - 1)
+    y = yd[a] + (f / L) * (yd[nxt] - yd[a])
+    return np.where(a + 1 < nd, y, yd[a])
+
+
 def xcorr_proj_block_rate(s, k, C, D, r: int) -> np.ndarray:
     """Block-rate projected valid cross-correlation (Sec. III-A: results may be
     omitted and interpolated from their neighbours; Sec. IV-A: one projection
@@ -417,11 +427,22 @@ def xcorr_proj_block_rate(s, k, C, D, r: int) -> np.ndarray:
     nout = s.size - k.size + 1
     nd = (nout - 1) // L + 1
     yd = xcorr_proj_at(s, k, C, D, r, np.arange(nd, dtype=np.int64) * L)
-    m = np.arange(nout)
-    a, f = m // L, m % L
-    nxt = np.minimum(a + 1, nd - 1)
-    y = yd[a] + (f / L) * (yd[nxt] - yd[a])
-    return np.where(a + 1 < nd, y, yd[a])
+    return _interpolate_block_rate(yd, np.arange(nout), L)
+
+
+def xcorr_proj_block_rate_at(s, k, C, D, r: int, ms) -> np.ndarray:
+    """xcorr_proj_block_rate at the output positions ms only (the computed
+    samples they need are evaluated one by one)."""
+    s, k = _f64(s), _f64(k)
+    L = _f64(C).shape[0]
+    nout = s.size - k.size + 1
+    nd = (nout - 1) // L + 1
+    ms = np.asarray(ms, dtype=np.int64)
+    need = np.unique(np.concatenate([ms // L, np.minimum(ms // L + 1, nd - 1)]))
+    vals = xcorr_proj_at(s, k, C, D, r, need * L)
+    yd = np.zeros(nd)
+    yd[need] = vals
+    return _interpolate_block_rate(yd, ms, L)
 
 
 # -------------------------------------------------------- metrics and counts

@@ -690,4 +690,37 @@ int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, c
     return launch_conv(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
 }
 
+size_t pj_conv1d_rate_workspace_bytes(int64_t W, int N, int L, int r, int rate, int prec)
+{
+    if (rate == PJ_RATE_FULL) return pj_conv1d_workspace_bytes(W, N, L, r, prec);
+    if (rate != PJ_RATE_BLOCK) return 0;
+    if (W < 1 || N < 1 || N > W || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
+    return (size_t)conv_block_geom(W, N, L, r).total;
+}
+
+int proj_conv1d_rate(pj_basis b, int r, int mode, int rate, int64_t W, const float* s, int N, const float* k,
+                     float* y, int prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (rate == PJ_RATE_FULL) return proj_conv1d(b, r, mode, W, s, N, k, y, prec, ws, ws_bytes, stream);
+    if (rate != PJ_RATE_BLOCK) return PJ_ERR_ARG;
+    if (!b || !s || !k || !y) return PJ_ERR_ARG;
+    if (r < 1 || r > b->L) return PJ_ERR_ARG;
+    if (mode != PJ_XCORR && mode != PJ_CONV) return PJ_ERR_ARG;
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    if (W < 1 || N < 1 || N > W) return PJ_ERR_SHAPE;
+    if (prec != PJ_F32) return PJ_ERR_UNSUPPORTED;
+    const ConvBlockGeom g = conv_block_geom(W, N, b->L, r);
+    if (cdiv(g.nbp, 128) > 0x7fffffff || cdiv((int64_t)r * g.ncb, 256) > 0x7fffffff || cdiv(g.nout, 256) > 0x7fffffff)
+        return PJ_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < (size_t)g.total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    ConvArgs a;
+    a.s = s; a.W = W; a.k = k; a.N = N;
+    a.reverse = (mode == PJ_CONV);
+    a.L = b->L; a.r = r;
+    a.C = b->Cf; a.DT = b->DTf;
+    a.y = y; a.ws = ws;
+    return launch_conv_block(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
+}
+
 }  // extern "C"

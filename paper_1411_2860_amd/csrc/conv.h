@@ -32,4 +32,15 @@ struct ConvArgs {
 };
 int launch_conv(const ConvArgs& a, hipStream_t s);
 
+// Block rate: outputs at m = aL only (nd of them), the rest interpolated.
+struct ConvBlockGeom {
+    int64_t nout;      // W - N + 1 outputs
+    int64_t nd;        // computed outputs a = 0 .. nd - 1 (m = aL <= W - N)
+    int64_t ncb;       // aligned kernel blocks ceil(N / L)
+    int64_t nbp;       // length of each projected-signal row (>= nd + ncb)
+    int64_t sc_bytes, kd_bytes, yd_bytes, total;
+};
+ConvBlockGeom conv_block_geom(int64_t W, int64_t N, int L, int r);
+int launch_conv_block(const ConvArgs& a, hipStream_t s);
+
 }  // namespace pj

@@ -350,6 +350,60 @@ __global__ __launch_bounds__(256) void split_sum_kernel(const float* __restrict_
     y[m] = v;
 }
 
+// ---- block rate: outputs at m = aL only, the others interpolated -------------
+// kd0[l][c] = sum_u D[l, u] k'(cL + u): the aligned kernel blocks projected
+// with the rows of D (phase b = 0 of step 2).
+__global__ __launch_bounds__(256) void kblock_kernel(const float* __restrict__ k, int64_t N, int reverse, int L, int r,
+                                                     int64_t ncb, const float* __restrict__ DT, float* __restrict__ kd0)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)r * ncb) return;
+    const int l = (int)(idx / ncb);
+    const int64_t c = idx - (int64_t)l * ncb;
+    float acc = 0.0f;
+#pragma unroll 8
+    for (int u = 0; u < L; ++u) {
+        const int64_t n = c * L + u;
+        const float kv = n < N ? (reverse ? k[N - 1 - n] : k[n]) : 0.0f;
+        acc += DT[(int64_t)u * L + l] * kv;
+    }
+    kd0[idx] = acc;
+}
+
+// yd[a] = sum_l sum_{c < ncb} sc_l[a + c] kd0[l][c]: the b = 0 column of the
+// reduced cross-correlation, one thread per computed output, highest
+// projection first with one partial sum per projection.
+__global__ __launch_bounds__(256) void xcorr_block_kernel(const float* __restrict__ sc, int64_t nbp,
+                                                          const float* __restrict__ kd0, int64_t ncb, int r, int64_t nd,
+                                                          float* __restrict__ yd)
+{
+    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (a >= nd) return;
+    float tot = 0.0f;
+    for (int l = r - 1; l >= 0; --l) {
+        const float* sp = sc + (int64_t)l * nbp + a;
+        const float* kp = kd0 + (int64_t)l * ncb;
+        float part = 0.0f;
+#pragma unroll 8
+        for (int64_t c = 0; c < ncb; ++c) part += sp[c] * kp[c];
+        tot += part;
+    }
+    yd[a] = tot;
+}
+
+// y[aL + f] = yd[a] + (f / L)(yd[a + 1] - yd[a]) while a + 1 < nd, else yd[a].
+__global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ yd, int64_t nd, int L, int64_t nout,
+                                                     float* __restrict__ y)
+{
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= nout) return;
+    const int64_t a = m / L;
+    const int f = (int)(m - a * L);
+    float v = yd[a];
+    if (f != 0 && a + 1 < nd) v += ((float)f / (float)L) * (yd[a + 1] - v);
+    y[m] = v;
+}
+
 // tile shapes: 128 x 256 (8 waves) when L > 128, else 128 x 128 (4 waves)
 constexpr int XW_M = 2, XW_N = 2, XWAVES_M = 2;
 constexpr int XBM = 32 * XW_M * XWAVES_M;
@@ -384,22 +438,26 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
     return g;
 }
 
+// Step 1 for both rates: sc_l[i] for l < r, i < nbp.
+static int launch_sig_project(const ConvArgs& a, float* sc, int64_t nbp, hipStream_t st)
+{
+    if (a.L > kMaxConvL) return -2;
+    dim3 grid((unsigned)cdiv(nbp, 128), (unsigned)cdiv(a.r, 32));
+    const bool vec = a.L % 4 == 0 && ((uintptr_t)a.s % 16) == 0;
+    if (vec)
+        hipLaunchKernelGGL((sig_project_kernel<4, true>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, nbp);
+    else
+        hipLaunchKernelGGL((sig_project_kernel<4, false>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, nbp);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_conv(const ConvArgs& a, hipStream_t st)
 {
     const ConvGeom g = conv_geom(a.W, a.N, a.L, a.r);
     float* sc = (float*)a.ws;
     char* kp = (char*)a.ws + g.sc_bytes;
     // step 1
-    {
-        if (a.L > kMaxConvL) return -2;
-        dim3 grid((unsigned)cdiv(g.nbp, 128), (unsigned)cdiv(a.r, 32));
-        const bool vec = a.L % 4 == 0 && ((uintptr_t)a.s % 16) == 0;
-        if (vec)
-            hipLaunchKernelGGL((sig_project_kernel<4, true>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, g.nbp);
-        else
-            hipLaunchKernelGGL((sig_project_kernel<4, false>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, g.nbp);
-        if (hipGetLastError() != hipSuccess) return -1;
-    }
+    if (launch_sig_project(a, sc, g.nbp, st) != 0) return -1;
     // step 2
     {
         if (a.L % 32 != 0) {
@@ -430,6 +488,38 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
         }
     }
     return 0;
+}
+
+ConvBlockGeom conv_block_geom(int64_t W, int64_t N, int L, int r)
+{
+    ConvBlockGeom g;
+    g.nout = W - N + 1;
+    g.nd = (g.nout - 1) / L + 1;
+    g.ncb = cdiv(N, L);
+    g.nbp = rup(g.nd + g.ncb, 128);
+    g.sc_bytes = rup((int64_t)r * g.nbp * 4, 256);
+    g.kd_bytes = rup((int64_t)r * g.ncb * 4, 256);
+    g.yd_bytes = rup(g.nd * 4, 256);
+    g.total = g.sc_bytes + g.kd_bytes + g.yd_bytes;
+    return g;
+}
+
+int launch_conv_block(const ConvArgs& a, hipStream_t st)
+{
+    const ConvBlockGeom g = conv_block_geom(a.W, a.N, a.L, a.r);
+    float* sc = (float*)a.ws;
+    float* kd0 = (float*)((char*)a.ws + g.sc_bytes);
+    float* yd = (float*)((char*)a.ws + g.sc_bytes + g.kd_bytes);
+    if (launch_sig_project(a, sc, g.nbp, st) != 0) return -1;
+    hipLaunchKernelGGL(kblock_kernel, dim3((unsigned)cdiv((int64_t)a.r * g.ncb, 256)), dim3(256), 0, st, a.k, a.N,
+                       a.reverse, a.L, a.r, g.ncb, a.DT, kd0);
+    if (hipGetLastError() != hipSuccess) return -1;
+    hipLaunchKernelGGL(xcorr_block_kernel, dim3((unsigned)cdiv(g.nd, 256)), dim3(256), 0, st, sc, g.nbp, kd0, g.ncb,
+                       a.r, g.nd, yd);
+    if (hipGetLastError() != hipSuccess) return -1;
+    hipLaunchKernelGGL(interp_kernel, dim3((unsigned)cdiv(g.nout, 256)), dim3(256), 0, st, yd, g.nd, a.L, g.nout,
+                       a.y);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace pj

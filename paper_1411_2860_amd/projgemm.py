@@ -70,6 +70,8 @@ _SIGNATURES = {
     "proj_gemm_backward": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                                 _i64, _i, _vp, _sz, _vp]),
     "proj_conv1d": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
+    "pj_conv1d_rate_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i, _i]),
+    "proj_conv1d_rate": (_i, [_vp, _i, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
 }
 
 
@@ -272,13 +274,18 @@ def gemm_packed(Ap, Bp, r: int, M: int, W: int, K: int, L: int, rmax_a: int, rma
     return out
 
 
-def conv1d_workspace_bytes(W: int, N: int, L: int, r: int, prec="f32") -> int:
-    return int(lib().pj_conv1d_workspace_bytes(W, N, L, r, _prec(prec)))
+_RATES = {"full": 0, "block": 1}
 
 
-def conv1d(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, workspace=None, stream=None):
+def conv1d_workspace_bytes(W: int, N: int, L: int, r: int, prec="f32", rate="full") -> int:
+    return int(lib().pj_conv1d_rate_workspace_bytes(W, N, L, r, _RATES[rate], _prec(prec)))
+
+
+def conv1d(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, workspace=None, stream=None, rate="full"):
     """Projected valid cross-correlation (mode 'xcorr') or convolution
-    ('conv') of the 1-D float32 CUDA tensors s (W) and k (N): W - N + 1 outputs."""
+    ('conv') of the 1-D float32 CUDA tensors s (W) and k (N): W - N + 1 outputs.
+    rate 'full' computes every output; 'block' computes the outputs at m = aL
+    and interpolates the others linearly (proj_conv1d_rate)."""
     import torch
     Wn, N = s.numel(), k.numel()
     if s.dtype != torch.float32 or k.dtype != torch.float32:
@@ -287,11 +294,12 @@ def conv1d(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, works
         raise ValueError("s and k must be contiguous")
     if out is None:
         out = torch.empty(max(Wn - N + 1, 1), dtype=torch.float32, device=s.device)
-    need = conv1d_workspace_bytes(Wn, N, basis.L, r, prec)
+    need = conv1d_workspace_bytes(Wn, N, basis.L, r, prec, rate)
     if workspace is None:
         workspace = _byte_buffer(need, s.device)
-    _check(lib().proj_conv1d(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], Wn, _ptr(s), N, _ptr(k), _ptr(out),
-                             _prec(prec), _ptr(workspace), workspace.numel(), _stream(stream)), "proj_conv1d")
+    _check(lib().proj_conv1d_rate(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], _RATES[rate], Wn, _ptr(s), N,
+                                  _ptr(k), _ptr(out), _prec(prec), _ptr(workspace), workspace.numel(),
+                                  _stream(stream)), "proj_conv1d_rate")
     return out
 
 

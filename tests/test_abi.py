@@ -193,3 +193,39 @@ def test_batched_validation(lib, basis16):
     assert lib.proj_gemm_batched(b.handle, 4, 2, ct.cast(nul, ct.c_void_p), 0.0, 1, -1, FAKE, n, None) == ARG
     # the workspace grows with the batch
     assert pg.gemm_batched_workspace_bytes((D * 3)(good, good, good), 16, 4, "f32") > n
+
+
+def test_conv_validation(lib, basis16):
+    """proj_conv1d and proj_conv1d_rate: every argument error is reported
+    before any device work; a valid call without a device reports PJ_ERR_HIP."""
+    b = basis16
+    W, N = 1000, 37
+    full = lib.pj_conv1d_workspace_bytes(W, N, 16, 4, 1)
+    blk = lib.pj_conv1d_rate_workspace_bytes(W, N, 16, 4, 1, 1)
+    assert full > 0 and blk > 0
+    assert lib.pj_conv1d_rate_workspace_bytes(W, N, 16, 4, 0, 1) == full
+    assert lib.pj_conv1d_rate_workspace_bytes(W, N, 16, 4, 2, 1) == 0          # unknown rate
+    assert lib.pj_conv1d_rate_workspace_bytes(W, W + 1, 16, 4, 1, 1) == 0      # N > W
+    assert lib.pj_conv1d_rate_workspace_bytes(W, N, 16, 17, 1, 1) == 0         # r > L
+
+    def call(rate, r=4, mode=0, Wc=W, Nc=N, s=FAKE, k=FAKE, y=FAKE, prec=1, ws_bytes=None, h=b.handle):
+        n = (full if rate == 0 else blk) if ws_bytes is None else ws_bytes
+        return lib.proj_conv1d_rate(h, r, mode, rate, Wc, s, Nc, k, y, prec, FAKE, n, None)
+
+    for rate in (0, 1):
+        assert call(rate, h=None) == ARG
+        assert call(rate, r=0) == ARG
+        assert call(rate, r=17) == ARG
+        assert call(rate, mode=2) == ARG
+        assert call(rate, s=None) == ARG
+        assert call(rate, y=None) == ARG
+        assert call(rate, prec=42) == ARG
+        assert call(rate, Nc=0) == SHAPE
+        assert call(rate, Nc=W + 1) == SHAPE
+        assert call(rate, Wc=0, Nc=1) == SHAPE
+        assert call(rate, prec=2) == UNSUP
+        assert call(rate, ws_bytes=(full if rate == 0 else blk) - 1) == WS
+        assert call(rate) == HIP
+    assert call(5) == ARG
+    assert lib.proj_conv1d(b.handle, 4, 0, W, FAKE, N, FAKE, FAKE, 1, FAKE, full - 1, None) == WS
+    assert lib.proj_conv1d(b.handle, 4, 0, W, FAKE, N, FAKE, FAKE, 1, FAKE, full, None) == HIP

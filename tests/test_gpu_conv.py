@@ -134,3 +134,80 @@ def test_split_contraction_every_output(pg, W, N, L, r):
     s = inputs.ar2_signal(W, seed=27)
     k, _ = inputs.excerpt_kernel(s, N, seed=28)
     _check(pg, s, k, "dct2", L, r)
+
+
+# ---- block rate: outputs at m = aL, the rest interpolated ----------------------
+
+def _check_block(pg, s, k, kind, L, r, mode="xcorr"):
+    basis = pg.Basis(kind, L)
+    C, D = basis.matrices()
+    y = pg.conv1d(_dev(s), _dev(k), r, basis, mode=mode, rate="block")
+    torch.cuda.synchronize()
+    got = y.double().cpu().numpy()
+    kk = k[::-1] if mode == "conv" else k
+    ref = oracle.xcorr_proj_block_rate(s, kk, C, D, r)
+    mag = oracle.xcorr_proj_block_rate(np.abs(s), np.abs(kk), np.abs(C), np.abs(D), r)
+    _tol.assert_within(got, ref, block_bound(L, r, k.size, mag), f"block {kind} L={L} r={r} N={k.size} {mode}")
+    return got, ref
+
+
+def block_bound(L, r, N, mag, safety=4.0):
+    """The computed samples sum r * ceil(N / L) products of two L-term FP32
+    dot products; the interpolation is a convex combination of two of them
+    (its own three roundings add at most 3u of the magnitude)."""
+    u = _tol.U["f32"]
+    g = lambda m: m * u / (1 - m * u)
+    return safety * (2 * g(L) + g(r * -(-N // L)) + 4 * u) * mag
+
+
+@pytest.mark.parametrize("L", [2, 4])
+@pytest.mark.parametrize("N", [600, 1200])
+def test_block_rate_paper_operating_points(pg, L, N):
+    """Block of 20000 samples, kernels of 600 / 1200 samples, Haar L = 2 and 4:
+    one projection at the block rate (half the sampling rate for L = 2,
+    missing samples interpolated) and all projections at the block rate."""
+    s = inputs.ar2_signal(20000, seed=23)
+    k, _ = inputs.excerpt_kernel(s, N, seed=24)
+    for r in (1, L):
+        _check_block(pg, s, k, "haar", L, r)
+
+
+@pytest.mark.parametrize("W,N,L,kind", [
+    (1000, 1, 8, "dct2"),       # N = 1
+    (257, 257, 16, "dct2"),     # one output
+    (999, 37, 16, "haar"),      # nothing aligned
+    (513, 64, 1, "identity"),   # L = 1: every output computed
+    (4099, 300, 256, "dct2"),   # largest L
+    (700, 33, 5, "dct2"),       # L not a power of two
+])
+def test_block_rate_ragged(pg, W, N, L, kind):
+    rng = np.random.default_rng(W + N + 1)
+    s, k = rng.standard_normal(W), rng.standard_normal(N)
+    for r in sorted({1, max(1, L // 2), L}):
+        _check_block(pg, s, k, kind, L, r)
+
+
+def test_block_rate_convolution_mode(pg):
+    s = inputs.ar2_signal(5000, seed=29)
+    k, _ = inputs.excerpt_kernel(s, 200, seed=30)
+    _check_block(pg, s, k, "haar", 2, 1, mode="conv")
+
+
+@pytest.mark.parametrize("r", [16, 256])
+def test_block_rate_full_size_sampled(pg, long_signal, r):
+    """2^22 samples, N = 16384, L = 256: sampled outputs (computed ones,
+    interpolated ones and the held tail) against the oracle."""
+    s = long_signal
+    N = 16384
+    k, o = inputs.excerpt_kernel(s, N, seed=inputs.SEED_KERNEL)
+    basis = pg.Basis("dct2", 256)
+    C, D = basis.matrices()
+    y = pg.conv1d(_dev(s), _dev(k), r, basis, rate="block")
+    torch.cuda.synchronize()
+    nout = s.size - N + 1
+    rng = np.random.default_rng(r + 7)
+    ms = np.unique(np.concatenate([[0, 1, 255, 256, 257, nout - 1, nout - 2, o], rng.integers(0, nout, 200)]))
+    got = y[torch.from_numpy(ms).cuda()].double().cpu().numpy()
+    ref = oracle.xcorr_proj_block_rate_at(s, k, C, D, r, ms)
+    mag = oracle.xcorr_proj_block_rate_at(np.abs(s), np.abs(k), np.abs(C), np.abs(D), r, ms)
+    _tol.assert_within(got, ref, block_bound(256, r, N, mag), f"block full size r={r}")

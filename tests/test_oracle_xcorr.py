@@ -168,3 +168,11 @@ def test_block_rate_half_samples_error_is_interpolation_error():
     odd = np.arange(1, exact.size - 1, 2)
     second = np.abs(exact[odd - 1] - 2 * exact[odd] + exact[odd + 1]) / 2
     assert np.all(np.abs(y[odd] - exact[odd]) <= second + 1e-9)
+
+
+def test_block_rate_sampled_equals_full():
+    C, D = oracle.basis("dct2", 8)
+    s, k = _rand(500, 14), _rand(60, 15)
+    full = oracle.xcorr_proj_block_rate(s, k, C, D, 3)
+    ms = np.array([0, 1, 7, 8, 9, 200, 433, 437, 440])
+    np.testing.assert_allclose(oracle.xcorr_proj_block_rate_at(s, k, C, D, 3, ms), full[ms], rtol=0, atol=0)
