@@ -28,6 +28,7 @@ __all__ = [
     "gemm_proj_closed", "gemm_proj_brute", "q_matrix", "blockdiag", "gemm_proj_grad_block",
     "project_signal", "project_kernel", "xcorr_proj", "xcorr_proj_at",
     "xcorr_proj_closed", "xcorr_proj_sliding", "xcorr_proj_block_rate", "xcorr_proj_block_rate_at",
+    "block_moments", "block_moments_brute", "basis_klt",
     "rel_fro", "snr_db", "work_gemm_plain", "work_gemm_proj",
     "work_conv_plain_time", "work_conv_proj_time",
 ]
@@ -443,6 +444,54 @@ def xcorr_proj_block_rate_at(s, k, C, D, r: int, ms) -> np.ndarray:
     yd = np.zeros(nd)
     yd[need] = vals
     return _interpolate_block_rate(yd, ms, L)
+
+
+# ------------------------------------------------ data-adaptive (KLT) basis
+
+def block_moments(X, L: int) -> np.ndarray:
+    """Second-moment matrix of the aligned L-blocks of the rows of X (K
+    zero-extended to a multiple of L): M[t, u] = sum_i sum_j X[i, jL+t] X[i, jL+u].
+    One library product (numpy.matmul) over the stacked blocks."""
+    X = _f64(X)
+    rows, K = X.shape
+    G = -(-K // L)
+    Xp = np.zeros((rows, G * L))
+    Xp[:, :K] = X
+    Xb = Xp.reshape(rows * G, L)
+    return Xb.T @ Xb
+
+
+def block_moments_brute(X, L: int) -> np.ndarray:
+    """block_moments by plain Python loops (tiny inputs)."""
+    X = np.asarray(X, dtype=np.float64)
+    rows, K = X.shape
+    G = -(-K // L)
+    M = [[0.0] * L for _ in range(L)]
+    for i in range(rows):
+        for j in range(G):
+            blk = [X[i, j * L + t] if j * L + t < K else 0.0 for t in range(L)]
+            for t in range(L):
+                for u in range(L):
+                    M[t][u] += blk[t] * blk[u]
+    return np.array(M)
+
+
+def basis_klt(M):
+    """Karhunen-Loeve (principal component) basis of a symmetric positive
+    semidefinite L x L second-moment matrix: the columns of C are its
+    eigenvectors ordered by decreasing eigenvalue (numpy.linalg.eigh), each
+    with its largest-magnitude entry made positive; C is orthonormal, so
+    D = C^{-1} = C^T.  Returns (C, D, eigenvalues)."""
+    M = _f64(M)
+    M = (M + M.T) / 2
+    w, V = np.linalg.eigh(M)
+    order = np.argsort(-w, kind="stable")
+    w, V = w[order], V[:, order]
+    for j in range(V.shape[1]):
+        i = int(np.argmax(np.abs(V[:, j])))
+        if V[i, j] < 0:
+            V[:, j] = -V[:, j]
+    return V, V.T.copy(), w
 
 
 # -------------------------------------------------------- metrics and counts
