@@ -39,7 +39,7 @@ PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500
 MFMA_PER_PRODUCT = {"bf16x3": 3, "f16x3": 3, "fp8x2": 3}
 PEAK_HBM = 8000.0                            # GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f32_recognition_traffic.md")
-SECTIONS = ["sweep", "precisions", "plain", "conv", "batched", "mlp"]
+SECTIONS = ["sweep", "precisions", "plain", "klt", "conv", "batched", "mlp"]
 
 
 def log(msg):
@@ -248,6 +248,36 @@ def main():
             del R_p
         return res
 
+    def sec_klt():
+        # data-adaptive basis: block second moments of 2048 database images on
+        # the device, eigenbasis on the host; then the headline workload with
+        # that basis against the DCT-II at each r (sampled errors vs FP64)
+        train = Bd[:2048]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Mm = pg.block_moments(train, L)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kb, eig = pg.klt_basis(Mm)
+        t2 = time.perf_counter()
+        Ck, Dk = kb.matrices()
+        res = {"train_images": 2048, "moments_ms": round((t1 - t0) * 1e3, 3),
+               "eigen_host_ms": round((t2 - t1) * 1e3, 3), "points": []}
+        import oracle
+        for rr in (1, 2, 4, 8, 16):
+            ms_k, kms_k, R_k, cfg_k = timed(rr, "f32", 10, 3, b=kb, Lb=L)
+            got = R_k[torch.from_numpy(srows).to(dev)][:, torch.from_numpy(scols).to(dev)].double().cpu().numpy()
+            e_klt = oracle.rel_fro(got, exact_block)
+            proj = oracle.gemm_proj_block(A, np.ascontiguousarray(Bt.T), Ck, Dk, rr, srows, scols)
+            ms_d, _, R_d, _ = timed(rr, "f32", 10, 3)
+            e_dct, _, _ = sampled_errors(rr, R_d)
+            res["points"].append({"r": rr, "klt_ms_per_step": round(ms_k, 5), "dct_ms_per_step": round(ms_d, 5),
+                                  "rel_err_vs_fp64_exact_klt": f3(e_klt), "rel_err_vs_fp64_exact_dct": f3(e_dct),
+                                  "rel_err_klt_vs_fp64_projected": f3(oracle.rel_fro(got, proj)),
+                                  "tile_cfg": cfg_k})
+            del R_k, R_d
+        return res
+
     def sec_plain():
         # plain (unprojected) FP32 GEMM through the same kernels: the identity
         # basis with all projections kept only permutes the contraction index
@@ -404,6 +434,7 @@ def main():
     section("sweep", sec_sweep)
     section("precisions", sec_precisions)
     section("plain", sec_plain)
+    section("klt", sec_klt)
     section("conv", sec_conv)
     section("batched", sec_batched)
     section("mlp", sec_mlp)

@@ -267,6 +267,39 @@ size_t pj_conv1d_rate_workspace_bytes(int64_t W, int N, int L, int r, int rate, 
 int proj_conv1d_rate(pj_basis b, int r, int mode, int rate, int64_t W, const float* s, int N, const float* k,
                      float* y, int prec, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- data-adaptive (Karhunen-Loeve) basis ------------------------------------
+ * The paper uses fixed bases (DCT-II, Haar) and names projection coefficients
+ * derived offline from training data by principal component analysis as the
+ * route to higher precision at fewer projections (Sec. IV-B footnote, Sec. VI).
+ * These two calls build such a basis: the block second moments of training
+ * rows on the device, then an orthonormal eigenbasis on the host. */
+
+/* Bytes of workspace pj_block_moments needs (0 for invalid arguments). */
+size_t pj_block_moments_workspace_bytes(int64_t rows, int64_t K, int L);
+
+/* M[t, u] = sum_i sum_j X[i, jL + t] X[i, jL + u]  (t, u < L): the second-moment
+ * matrix of the aligned L-blocks of the rows of X (K zero-extended to a
+ * multiple of L), accumulated in FP64.
+ *   X : device FP32, rows x K row-major, leading dimension ld >= K.
+ *   M : device FP64, L x L row-major, overwritten.
+ * Errors: PJ_ERR_ARG (null pointer, L outside 1..256), PJ_ERR_SHAPE (rows,
+ * K < 1 or ld < K), PJ_ERR_WORKSPACE, PJ_ERR_HIP.  Asynchronous on `stream`. */
+int pj_block_moments(int L, int64_t rows, int64_t K, const float* X, int64_t ld, double* M, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Orthonormal basis from a symmetric positive semidefinite L x L matrix M
+ * (host FP64, row-major; typically pj_block_moments' result copied to the
+ * host): the columns of C are the eigenvectors of M in order of decreasing
+ * eigenvalue (cyclic Jacobi rotations in FP64), each with its largest-
+ * magnitude entry positive, and D = C^T.  With this basis the first r
+ * projections keep the largest possible share of the training blocks' energy
+ * (the residual is the sum of the eigenvalues past r).
+ *   eig_out : host, L doubles in the same order, or NULL.
+ * The basis is used like any other (kind reported as PJ_BASIS_CUSTOM).
+ * Errors: PJ_ERR_ARG (null out or M, L outside 1..256, non-finite or
+ * non-symmetric M).  Uploads synchronously, like pj_basis_create. */
+int pj_basis_create_klt(pj_basis* out, int L, const double* M, double* eig_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@
 
 #include "common.h"
 #include "conv.h"
+#include "moments.h"
 
 using namespace pj;
 
@@ -67,6 +68,50 @@ void make_haar(int L, std::vector<double>& C)
 }
 
 // D = C^{-1} by LU with partial pivoting; false if C is (numerically) singular.
+// Eigen-decomposition of a symmetric L x L matrix by cyclic Jacobi rotations
+// in FP64: on return A is (numerically) diagonal with the eigenvalues and the
+// columns of V are the eigenvectors.  Each rotation J in the (p, q) plane
+// (J_pp = J_qq = c, J_pq = s, J_qp = -s) is chosen so that (J^T A J)_pq = 0,
+// with the smaller of the two rotation angles.
+void jacobi_eig(int L, std::vector<double>& A, std::vector<double>& V)
+{
+    V.assign((size_t)L * L, 0.0);
+    for (int i = 0; i < L; ++i) V[(size_t)i * L + i] = 1.0;
+    auto a = [&](int i, int j) -> double& { return A[(size_t)i * L + j]; };
+    double total = 0.0;
+    for (double x : A) total += x * x;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < L; ++p)
+            for (int q = 0; q < L; ++q)
+                if (p != q) off += a(p, q) * a(p, q);
+        if (off <= 1e-30 * total || off == 0.0) break;
+        for (int p = 0; p < L - 1; ++p)
+            for (int q = p + 1; q < L; ++q) {
+                const double apq = a(p, q);
+                if (apq == 0.0) continue;
+                const double tau = (a(q, q) - a(p, p)) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+                for (int k = 0; k < L; ++k) {          // columns p, q: A J
+                    const double akp = a(k, p), akq = a(k, q);
+                    a(k, p) = c * akp - sn * akq;
+                    a(k, q) = sn * akp + c * akq;
+                }
+                for (int k = 0; k < L; ++k) {          // rows p, q: J^T (A J)
+                    const double apk = a(p, k), aqk = a(q, k);
+                    a(p, k) = c * apk - sn * aqk;
+                    a(q, k) = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < L; ++k) {          // V J
+                    const double vkp = V[(size_t)k * L + p], vkq = V[(size_t)k * L + q];
+                    V[(size_t)k * L + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * L + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+}
+
 bool invert_lu(int L, const std::vector<double>& C, std::vector<double>& D)
 {
     std::vector<double> a(C);
@@ -119,6 +164,12 @@ void free_device(pj_basis b)
     (void)hipFree(b->I4d);
     if (prev >= 0) (void)hipSetDevice(prev);
     b->on_device = false;
+}
+
+bool device_present()
+{
+    int ndev = 0;
+    return hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0;
 }
 
 bool upload(pj_basis b)
@@ -721,6 +772,67 @@ int proj_conv1d_rate(pj_basis b, int r, int mode, int rate, int64_t W, const flo
     a.C = b->Cf; a.DT = b->DTf;
     a.y = y; a.ws = ws;
     return launch_conv_block(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
+}
+
+int pj_basis_create_klt(pj_basis* out, int L, const double* M, double* eig_out)
+{
+    if (!out) return PJ_ERR_ARG;
+    *out = nullptr;
+    if (L < 1 || L > kMaxL || !M) return PJ_ERR_ARG;
+    const size_t n = (size_t)L * L;
+    double big = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        if (!std::isfinite(M[i])) return PJ_ERR_ARG;
+        big = std::max(big, std::fabs(M[i]));
+    }
+    for (int t = 0; t < L; ++t)
+        for (int u = t + 1; u < L; ++u)
+            if (std::fabs(M[(size_t)t * L + u] - M[(size_t)u * L + t]) > 1e-12 * big) return PJ_ERR_ARG;
+    std::vector<double> A(M, M + n), V;
+    jacobi_eig(L, A, V);
+    std::vector<int> order(L);
+    for (int i = 0; i < L; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return A[(size_t)x * L + x] > A[(size_t)y * L + y]; });
+    pj_basis b = new (std::nothrow) pj_basis_s;
+    if (!b) return PJ_ERR_ARG;
+    b->kind = PJ_BASIS_CUSTOM;
+    b->L = L;
+    b->C.assign(n, 0.0);
+    b->D.assign(n, 0.0);
+    for (int l = 0; l < L; ++l) {
+        const int src = order[l];
+        int imax = 0;
+        for (int t = 1; t < L; ++t)
+            if (std::fabs(V[(size_t)t * L + src]) > std::fabs(V[(size_t)imax * L + src])) imax = t;
+        const double sg = V[(size_t)imax * L + src] < 0.0 ? -1.0 : 1.0;
+        for (int t = 0; t < L; ++t) b->C[(size_t)t * L + l] = sg * V[(size_t)t * L + src];
+        if (eig_out) eig_out[l] = A[(size_t)src * L + src];
+    }
+    for (int t = 0; t < L; ++t)          // orthonormal: D = C^T
+        for (int l = 0; l < L; ++l) b->D[(size_t)l * L + t] = b->C[(size_t)t * L + l];
+    upload(b);
+    *out = b;
+    return PJ_OK;
+}
+
+size_t pj_block_moments_workspace_bytes(int64_t rows, int64_t K, int L)
+{
+    if (rows < 1 || K < 1 || L < 1 || L > kMaxL) return 0;
+    return (size_t)std::max<int64_t>(moments_geom(rows, K, L).ws_bytes, 256);
+}
+
+int pj_block_moments(int L, int64_t rows, int64_t K, const float* X, int64_t ld, double* M, void* ws,
+                     size_t ws_bytes, void* stream)
+{
+    if (!X || !M) return PJ_ERR_ARG;
+    if (L < 1 || L > kMaxL) return PJ_ERR_ARG;
+    if (rows < 1 || K < 1 || ld < K) return PJ_ERR_SHAPE;
+    const MomentsGeom g = moments_geom(rows, K, L);
+    if (g.chunk > 0x7fffffff || g.nchunk > 65535) return PJ_ERR_UNSUPPORTED;
+    if (g.ws_bytes > 0 && (!ws || ws_bytes < (size_t)g.ws_bytes)) return PJ_ERR_WORKSPACE;
+    if (!device_present()) return PJ_ERR_HIP;
+    return launch_moments(X, ld, rows, K, L, M, ws, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
 }
 
 }  // extern "C"

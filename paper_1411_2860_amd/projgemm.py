@@ -71,6 +71,9 @@ _SIGNATURES = {
                                 _i64, _i, _vp, _sz, _vp]),
     "proj_conv1d": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
     "pj_conv1d_rate_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i, _i]),
+    "pj_block_moments_workspace_bytes": (_sz, [_i64, _i64, _i]),
+    "pj_block_moments": (_i, [_i, _i64, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "pj_basis_create_klt": (_i, [ctypes.POINTER(_vp), _i, _dp, _dp]),
     "proj_conv1d_rate": (_i, [_vp, _i, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
 }
 
@@ -155,6 +158,38 @@ class Basis:
             self.close()
         except Exception:
             pass
+
+
+def block_moments(X, L: int, stream=None):
+    """FP64 L x L second moments of the aligned L-blocks of the rows of the
+    FP32 CUDA matrix X (pj_block_moments), as a CUDA float64 tensor."""
+    import torch
+    if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D float32 tensor with unit column stride")
+    rows, K = X.shape
+    M = torch.empty((L, L), dtype=torch.float64, device=X.device)
+    ws = _byte_buffer(int(lib().pj_block_moments_workspace_bytes(rows, K, L)), X.device)
+    _check(lib().pj_block_moments(L, rows, K, _ptr(X), X.stride(0), _ptr(M), _ptr(ws), ws.numel(), _stream(stream)),
+           "pj_block_moments")
+    return M
+
+
+def klt_basis(M):
+    """(Basis, eigenvalues) of the orthonormal eigenbasis of the symmetric
+    positive semidefinite L x L matrix M (numpy array or tensor; pj_basis_create_klt)."""
+    if hasattr(M, "detach"):
+        M = M.detach().double().cpu().numpy()
+    arr = np.ascontiguousarray(np.asarray(M, dtype=np.float64))
+    L = arr.shape[0]
+    if arr.shape != (L, L):
+        raise ValueError("M must be square")
+    b = Basis.__new__(Basis)
+    b._h = _vp()
+    eig = np.empty(L)
+    _check(lib().pj_basis_create_klt(ctypes.byref(b._h), L, arr.ctypes.data_as(_dp), eig.ctypes.data_as(_dp)),
+           "pj_basis_create_klt")
+    b.kind, b.L = "klt", L
+    return b, eig
 
 
 def packed_bytes(rows: int, K: int, L: int, rmax: int, prec="f32") -> int:

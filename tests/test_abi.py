@@ -229,3 +229,44 @@ def test_conv_validation(lib, basis16):
     assert call(5) == ARG
     assert lib.proj_conv1d(b.handle, 4, 0, W, FAKE, N, FAKE, FAKE, 1, FAKE, full - 1, None) == WS
     assert lib.proj_conv1d(b.handle, 4, 0, W, FAKE, N, FAKE, FAKE, 1, FAKE, full, None) == HIP
+
+
+@pytest.mark.parametrize("L", [1, 4, 8, 64])
+def test_klt_basis_matches_oracle(lib, L):
+    """pj_basis_create_klt (host Jacobi) against the oracle's eigenbasis: same
+    eigenvalues, orthonormal C with D = C^T, and the same projector Q_r at
+    every r past which the eigenvalues are separated."""
+    X = np.random.default_rng(L).standard_normal((40, 6 * L)) @ np.diag(np.linspace(1, 3, 6 * L))
+    M = oracle.block_moments(X, L)
+    b, eig = pg.klt_basis(M)
+    C, D = b.matrices()
+    Co, Do, wo = oracle.basis_klt(M)
+    np.testing.assert_allclose(eig, wo, rtol=1e-10, atol=1e-10 * wo[0])
+    np.testing.assert_allclose(C.T @ C, np.eye(L), atol=1e-12)
+    np.testing.assert_allclose(D, C.T, atol=0)
+    for r in range(1, L + 1):
+        if r == L or wo[r - 1] - wo[r] > 1e-6 * wo[0]:
+            np.testing.assert_allclose(oracle.q_matrix(C, D, r), oracle.q_matrix(Co, Do, r), atol=1e-9)
+    for l in range(L):                                   # sign rule: largest-magnitude entry positive
+        assert C[np.argmax(np.abs(C[:, l])), l] > 0
+
+
+def test_klt_and_moments_validation(lib):
+    h = pg._vp()
+    M = np.eye(4)
+    assert lib.pj_basis_create_klt(None, 4, M.ctypes.data_as(pg._dp), None) == ARG
+    assert lib.pj_basis_create_klt(ctypes.byref(h), 4, None, None) == ARG
+    assert lib.pj_basis_create_klt(ctypes.byref(h), 0, M.ctypes.data_as(pg._dp), None) == ARG
+    assert lib.pj_basis_create_klt(ctypes.byref(h), 257, M.ctypes.data_as(pg._dp), None) == ARG
+    bad = np.eye(4); bad[0, 1] = 1.0
+    assert lib.pj_basis_create_klt(ctypes.byref(h), 4, bad.ctypes.data_as(pg._dp), None) == ARG
+    nan = np.eye(4); nan[2, 2] = np.nan
+    assert lib.pj_basis_create_klt(ctypes.byref(h), 4, nan.ctypes.data_as(pg._dp), None) == ARG
+    n = lib.pj_block_moments_workspace_bytes(1000, 4096, 64)
+    assert n > 0 and lib.pj_block_moments_workspace_bytes(0, 4096, 64) == 0
+    assert lib.pj_block_moments(64, 1000, 4096, None, 4096, FAKE, FAKE, n, None) == ARG
+    assert lib.pj_block_moments(0, 1000, 4096, FAKE, 4096, FAKE, FAKE, n, None) == ARG
+    assert lib.pj_block_moments(64, 1000, 4096, FAKE, 4095, FAKE, FAKE, n, None) == SHAPE
+    assert lib.pj_block_moments(64, 0, 4096, FAKE, 4096, FAKE, FAKE, n, None) == SHAPE
+    assert lib.pj_block_moments(64, 1000, 4096, FAKE, 4096, FAKE, FAKE, n - 1, None) == WS
+    assert lib.pj_block_moments(64, 1000, 4096, FAKE, 4096, FAKE, FAKE, n, None) == HIP
