@@ -28,7 +28,7 @@ __all__ = [
     "gemm_proj_closed", "gemm_proj_brute", "q_matrix", "blockdiag", "gemm_proj_grad_block",
     "project_signal", "project_kernel", "xcorr_proj", "xcorr_proj_at",
     "xcorr_proj_closed", "xcorr_proj_sliding", "xcorr_proj_block_rate", "xcorr_proj_block_rate_at",
-    "block_moments", "block_moments_brute", "basis_klt",
+    "block_moments", "block_moments_brute", "basis_klt", "pca2d",
     "rel_fro", "snr_db", "work_gemm_plain", "work_gemm_proj",
     "work_conv_plain_time", "work_conv_proj_time",
 ]
@@ -492,6 +492,42 @@ def basis_klt(M):
         if V[i, j] < 0:
             V[:, j] = -V[:, j]
     return V, V.T.copy(), w
+
+
+# ------------------------------------------------------------------ 2D-PCA
+
+def pca2d(train, test, C, D, r: int, n_axes: int):
+    """2D-PCA with every matrix product of eq. (22)-(24) projected (Sec. V-A):
+      * training images A_j (m x n) and test images B_i have the training
+        mean image subtracted;
+      * scatter matrix G = sum_j A_j^T A_j (n x n; the orientation that makes
+        Y = A X well defined), one projected GEMM over the vertically stacked
+        training images (contraction over the image rows);
+      * projection axes X = the eigenvectors of G for its n_axes largest
+        eigenvalues (numpy.linalg.eigh, sign rule of basis_klt);
+      * features Y_set,j = A_j X and Y_test,i = B_i X, projected GEMMs over the
+        stacked images (contraction over the image columns);
+      * matching (eq. (25)): nearest training image in Frobenius distance,
+        computed exactly.
+    Returns dict with G, X, eigenvalues, Y_set (J x m x D), Y_test, dist
+    (tests x train squared distances) and match (index of the nearest
+    training image per test image, first index on ties)."""
+    train, test = _f64(train), _f64(test)
+    J, m, n = train.shape
+    T = test.shape[0]
+    mean = train.mean(axis=0)
+    A = (train - mean).reshape(J * m, n)
+    B = (test - mean).reshape(T * m, n)
+    G = gemm_proj(np.ascontiguousarray(A.T), A, C, D, r)
+    G = (G + G.T) / 2
+    Vx, _, w = basis_klt(G)
+    X = np.ascontiguousarray(Vx[:, :n_axes])
+    Ys = gemm_proj(A, X, C, D, r).reshape(J, m, n_axes)
+    Yt = gemm_proj(B, X, C, D, r).reshape(T, m, n_axes)
+    Fs, Ft = Ys.reshape(J, -1), Yt.reshape(T, -1)
+    dist = (Ft * Ft).sum(1)[:, None] + (Fs * Fs).sum(1)[None, :] - 2.0 * (Ft @ Fs.T)
+    return {"G": G, "X": X, "eig": w, "Y_set": Ys, "Y_test": Yt, "dist": dist,
+            "match": np.argmin(dist, axis=1)}
 
 
 # -------------------------------------------------------- metrics and counts

@@ -119,3 +119,31 @@ def batched_shapes(count: int = 64, lo: int = 128, hi: int = 4096, seed: int = S
     """count (M, W, K) triples drawn iid uniform on {lo .. hi}."""
     rng = np.random.default_rng(seed)
     return [tuple(int(v) for v in rng.integers(lo, hi + 1, size=3)) for _ in range(count)]
+
+
+SEED_FACES = 2205
+
+
+def face_classes(n_classes: int = 15, per_class: int = 11, side: int = 288, sigma_id: float = 8.0,
+                 sigma_var: float = 4.0, var_weight: float = 0.35, seed: int = SEED_FACES):
+    """Synthetic stand-in for a face database (Yale-A shape: 15 persons x 11
+    images, cropped to 288 x 288).  Class c has an identity field (smoothed
+    noise, sigma_id) shared by its images; image i of class c mixes it with
+    its own variation field (sigma_var) and a brightness offset:
+        img = (1 - var_weight) * id_c + var_weight * var_ci + offset_ci,
+    clipped to 0..255.  Returns (images n x side x side float64, labels n,
+    index within class n), classes in order."""
+    imgs = np.empty((n_classes * per_class, side, side))
+    labels = np.empty(n_classes * per_class, dtype=np.int64)
+    index = np.empty(n_classes * per_class, dtype=np.int64)
+    rng = np.random.default_rng(seed)
+    for c in range(n_classes):
+        ident = smoothed_field(side, side, sigma=sigma_id, seed=seed * 1000 + c)
+        for i in range(per_class):
+            var = smoothed_field(side, side, sigma=sigma_var, seed=seed * 100000 + c * 100 + i)
+            off = rng.uniform(-20.0, 20.0)
+            img = (1.0 - var_weight) * ident + var_weight * var + off
+            imgs[c * per_class + i] = np.clip(img, 0.0, 255.0)
+            labels[c * per_class + i] = c
+            index[c * per_class + i] = i
+    return imgs, labels, index
