@@ -39,7 +39,7 @@ PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500
 MFMA_PER_PRODUCT = {"bf16x3": 3, "f16x3": 3, "fp8x2": 3}
 PEAK_HBM = 8000.0                            # GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f32_recognition_traffic.md")
-SECTIONS = ["sweep", "precisions", "plain", "klt", "conv", "batched", "mlp"]
+SECTIONS = ["sweep", "precisions", "plain", "klt", "pca2d", "conv", "batched", "mlp"]
 
 
 def log(msg):
@@ -278,6 +278,37 @@ def main():
             del R_k, R_d
         return res
 
+    def sec_pca2d():
+        # 2D-PCA on the Yale-A shape (15 classes x 11 images of 288 x 288, the
+        # first 5 per class for training, 10 axes): the GEMMs of the scatter
+        # matrix and of the training / test features on one of L projections,
+        # against the same GEMMs exact; recognition rate of the full pipeline
+        from paper_1411_2860_amd.pca2d import PCA2D
+        imgs, labels, idx = inputs.face_classes()
+        tr = torch.from_numpy(imgs[idx < 5]).float().to(dev)
+        te = torch.from_numpy(imgs[idx >= 5]).float().to(dev)
+        ltr, lte = labels[idx < 5], labels[idx >= 5]
+        J, m, n = tr.shape
+        mean = tr.mean(0)
+        Ast = (tr - mean).reshape(J * m, n).contiguous()
+        Bst = (te - mean).reshape(te.shape[0] * m, n).contiguous()
+        out = []
+        for lab, b, rr in [("exact", pg.Basis("identity", 1), 1), ("dct2 L=8", pg.Basis("dct2", 8), 1),
+                           ("dct2 L=12", pg.Basis("dct2", 12), 1), ("dct2 L=16", pg.Basis("dct2", 16), 1)]:
+            model = PCA2D(b, rr, 10).fit(tr)
+            rate = float(np.mean(ltr[model.match(te).cpu().numpy()] == lte))
+            X = model.X
+            t_g = autotune._time_ms(lambda: pg.gemm(Ast, Ast, rr, b, transA=True), 20, warmup=3)
+            t_s = autotune._time_ms(lambda: pg.gemm(Ast, X, rr, b), 20, warmup=3)
+            t_t = autotune._time_ms(lambda: pg.gemm(Bst, X, rr, b), 20, warmup=3)
+            out.append({"basis": lab, "r": rr, "recognition_rate": round(rate, 4), "scatter_ms": round(t_g, 4),
+                        "train_features_ms": round(t_s, 4), "test_features_ms": round(t_t, 4),
+                        "gemm_total_ms": round(t_g + t_s + t_t, 4)})
+        ex = out[0]["gemm_total_ms"]
+        for o in out:
+            o["gemm_speedup_vs_exact"] = round(ex / o["gemm_total_ms"], 3)
+        return {"images": [int(J), int(te.shape[0]), int(m), int(n)], "axes": 10, "points": out}
+
     def sec_plain():
         # plain (unprojected) FP32 GEMM through the same kernels: the identity
         # basis with all projections kept only permutes the contraction index
@@ -435,6 +466,7 @@ def main():
     section("precisions", sec_precisions)
     section("plain", sec_plain)
     section("klt", sec_klt)
+    section("pca2d", sec_pca2d)
     section("conv", sec_conv)
     section("batched", sec_batched)
     section("mlp", sec_mlp)

@@ -300,6 +300,16 @@ int pj_block_moments(int L, int64_t rows, int64_t K, const float* X, int64_t ld,
  * non-symmetric M).  Uploads synchronously, like pj_basis_create. */
 int pj_basis_create_klt(pj_basis* out, int L, const double* M, double* eig_out);
 
+/* Eigen-decomposition of a symmetric n x n matrix on the host (the same FP64
+ * cyclic Jacobi rotations): w[l] are the eigenvalues in decreasing order and
+ * column l of V (row-major n x n) the matching unit eigenvector, its largest-
+ * magnitude entry positive.  Used for the projection axes of 2D-PCA (the
+ * eigenvectors of the image scatter matrix, paper Sec. V-A) and for any
+ * other principal-component step.  A, w, V are host arrays; n <= 4096.
+ * Errors: PJ_ERR_ARG (null pointer, n outside 1..4096, non-finite or
+ * non-symmetric A).  Cost O(n^3) per sweep. */
+int pj_sym_eig(int n, const double* A, double* w, double* V);
+
 #ifdef __cplusplus
 }
 #endif

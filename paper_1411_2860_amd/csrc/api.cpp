@@ -835,4 +835,34 @@ int pj_block_moments(int L, int64_t rows, int64_t K, const float* X, int64_t ld,
     return launch_moments(X, ld, rows, K, L, M, ws, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
 }
 
+int pj_sym_eig(int n, const double* A, double* w, double* V)
+{
+    if (n < 1 || n > 4096 || !A || !w || !V) return PJ_ERR_ARG;
+    const size_t nn = (size_t)n * n;
+    double big = 0.0;
+    for (size_t i = 0; i < nn; ++i) {
+        if (!std::isfinite(A[i])) return PJ_ERR_ARG;
+        big = std::max(big, std::fabs(A[i]));
+    }
+    for (int t = 0; t < n; ++t)
+        for (int u = t + 1; u < n; ++u)
+            if (std::fabs(A[(size_t)t * n + u] - A[(size_t)u * n + t]) > 1e-12 * big) return PJ_ERR_ARG;
+    std::vector<double> a(A, A + nn), v;
+    jacobi_eig(n, a, v);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return a[(size_t)x * n + x] > a[(size_t)y * n + y]; });
+    for (int l = 0; l < n; ++l) {
+        const int src = order[l];
+        int imax = 0;
+        for (int t = 1; t < n; ++t)
+            if (std::fabs(v[(size_t)t * n + src]) > std::fabs(v[(size_t)imax * n + src])) imax = t;
+        const double sg = v[(size_t)imax * n + src] < 0.0 ? -1.0 : 1.0;
+        for (int t = 0; t < n; ++t) V[(size_t)t * n + l] = sg * v[(size_t)t * n + src];
+        w[l] = a[(size_t)src * n + src];
+    }
+    return PJ_OK;
+}
+
 }  // extern "C"

@@ -74,6 +74,7 @@ _SIGNATURES = {
     "pj_block_moments_workspace_bytes": (_sz, [_i64, _i64, _i]),
     "pj_block_moments": (_i, [_i, _i64, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
     "pj_basis_create_klt": (_i, [ctypes.POINTER(_vp), _i, _dp, _dp]),
+    "pj_sym_eig": (_i, [_i, _dp, _dp, _dp]),
     "proj_conv1d_rate": (_i, [_vp, _i, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
 }
 
@@ -190,6 +191,22 @@ def klt_basis(M):
            "pj_basis_create_klt")
     b.kind, b.L = "klt", L
     return b, eig
+
+
+def sym_eig(A):
+    """(w, V) of the symmetric matrix A (numpy or tensor, moved to the host):
+    eigenvalues in decreasing order, unit eigenvectors as the columns of V
+    (pj_sym_eig)."""
+    if hasattr(A, "detach"):
+        A = A.detach().double().cpu().numpy()
+    a = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    n = a.shape[0]
+    if a.shape != (n, n):
+        raise ValueError("A must be square")
+    w = np.empty(n)
+    V = np.empty((n, n))
+    _check(lib().pj_sym_eig(n, a.ctypes.data_as(_dp), w.ctypes.data_as(_dp), V.ctypes.data_as(_dp)), "pj_sym_eig")
+    return w, V
 
 
 def packed_bytes(rows: int, K: int, L: int, rmax: int, prec="f32") -> int:
