@@ -211,6 +211,10 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
     constexpr int KB = ly.KB, RB = ly.RB;
     constexpr int Ec = Cmap<PREC>::Ec, NGc = Cmap<PREC>::NGc, TRc = Cmap<PREC>::TRc;
     using V4 = typename Vec4<TIn>::type;
+    // staged values per thread never exceed the LDS budget's: 16-byte groups
+    // of 4 values (contiguous path) and 4 x 4 blocks (strided path)
+    constexpr int kMaxV4 = kPackLdsBytes / (4 * (int)sizeof(TIn) * kPackThreads);
+    constexpr int kMaxV16 = kPackLdsBytes / (16 * (int)sizeof(TIn) * kPackThreads);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     TIn* lds = reinterpret_cast<TIn*>(smem_raw);
 
@@ -224,7 +228,8 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
     const int row = lane / NGc, g = lane % NGc;
     const int L = J.L, r = J.r, TC = J.TC, TCp = J.TCp, JS = J.JS, RS = J.RS;
     const TIn* __restrict__ X = J.X;
-    const TIn* __restrict__ coef = J.coef;
+    using ConstTIn = const __attribute__((address_space(4))) TIn;
+    ConstTIn* coefc = (ConstTIn*)(J.coef);
 
     for (int lp = 0; lp < r; lp += 4 * NCH * RL) {
         TIn acc[NCH][RL][Ec];
@@ -238,46 +243,75 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
         for (int t0 = 0; t0 < L; t0 += TC) {
             __syncthreads();
             if (J.vec4 && !J.trans) {
-                // 16-byte loads along the contiguous contraction index
+                // 16-byte loads along the contiguous contraction index; every
+                // load of a thread is issued before its first LDS store
                 const int n4 = TRc * KB * (TC / 4);
-                for (int idx = threadIdx.x; idx < n4; idx += kPackThreads) {
-                    const int tt4 = idx % (TC / 4);
-                    const int q = idx / (TC / 4);
-                    const int jj = q % KB, rr = q / KB;
-                    const int64_t p = p0 + rr;
-                    const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
-                    V4 v = {0, 0, 0, 0};
-                    if (p < J.P && k < J.K) v = *reinterpret_cast<const V4*>(X + p * J.ld + k);
-                    *reinterpret_cast<V4*>(lds + rr * RS + jj * JS + 4 * tt4) = v;
+                V4 buf[kMaxV4];
+#pragma unroll
+                for (int i = 0; i < kMaxV4; ++i) {
+                    const int idx = threadIdx.x + i * kPackThreads;
+                    buf[i] = V4{0, 0, 0, 0};
+                    if (idx < n4) {
+                        const int tt4 = idx % (TC / 4);
+                        const int q = idx / (TC / 4);
+                        const int jj = q % KB, rr = q / KB;
+                        const int64_t p = p0 + rr;
+                        const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
+                        if (p < J.P && k < J.K) buf[i] = *reinterpret_cast<const V4*>(X + p * J.ld + k);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kMaxV4; ++i) {
+                    const int idx = threadIdx.x + i * kPackThreads;
+                    if (idx < n4) {
+                        const int tt4 = idx % (TC / 4);
+                        const int q = idx / (TC / 4);
+                        const int jj = q % KB, rr = q / KB;
+                        *reinterpret_cast<V4*>(lds + rr * RS + jj * JS + 4 * tt4) = buf[i];
+                    }
                 }
             } else if (J.vec4) {
                 // strided source: 4 rows x 4 indices per thread, 16-byte loads
-                // along the rows, transposed in registers
+                // along the rows, transposed in registers (all loads first)
                 const int n16 = (TRc / 4) * KB * (TC / 4);
-                for (int idx = threadIdx.x; idx < n16; idx += kPackThreads) {
-                    const int rr4 = idx % (TRc / 4);
-                    const int q = idx / (TRc / 4);
-                    const int tt4 = q % (TC / 4), jj = q / (TC / 4);
-                    const int64_t p = p0 + 4 * rr4;
-                    const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
-                    V4 col[4];
+                V4 col[kMaxV16][4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        col[i] = V4{0, 0, 0, 0};
-                        if (k + i < J.K) {
-                            if (p + 3 < J.P) {
-                                col[i] = *reinterpret_cast<const V4*>(X + (k + i) * J.ld + p);
-                            } else {
+                for (int s = 0; s < kMaxV16; ++s) {
+                    const int idx = threadIdx.x + s * kPackThreads;
 #pragma unroll
-                                for (int u = 0; u < 4; ++u)
-                                    if (p + u < J.P) col[i][u] = X[(k + i) * J.ld + p + u];
+                    for (int i = 0; i < 4; ++i) col[s][i] = V4{0, 0, 0, 0};
+                    if (idx < n16) {
+                        const int rr4 = idx % (TRc / 4);
+                        const int q = idx / (TRc / 4);
+                        const int tt4 = q % (TC / 4), jj = q / (TC / 4);
+                        const int64_t p = p0 + 4 * rr4;
+                        const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (k + i < J.K) {
+                                if (p + 3 < J.P) {
+                                    col[s][i] = *reinterpret_cast<const V4*>(X + (k + i) * J.ld + p);
+                                } else {
+#pragma unroll
+                                    for (int u = 0; u < 4; ++u)
+                                        if (p + u < J.P) col[s][i][u] = X[(k + i) * J.ld + p + u];
+                                }
                             }
                         }
                     }
+                }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const V4 w = {col[0][u], col[1][u], col[2][u], col[3][u]};
-                        *reinterpret_cast<V4*>(lds + (4 * rr4 + u) * RS + jj * JS + 4 * tt4) = w;
+                for (int s = 0; s < kMaxV16; ++s) {
+                    const int idx = threadIdx.x + s * kPackThreads;
+                    if (idx < n16) {
+                        const int rr4 = idx % (TRc / 4);
+                        const int q = idx / (TRc / 4);
+                        const int tt4 = q % (TC / 4), jj = q / (TC / 4);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const V4 w = {col[s][0][u], col[s][1][u], col[s][2][u], col[s][3][u]};
+                            *reinterpret_cast<V4*>(lds + (4 * rr4 + u) * RS + jj * JS + 4 * tt4) = w;
+                        }
                     }
                 }
             } else {
@@ -305,16 +339,20 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
             __syncthreads();
             for (int tt4 = 0; tt4 < TCp / 4; ++tt4) {
                 const int tb = t0 + 4 * tt4;
+                // wave-uniform coefficients through the constant address space
+                // (scalar loads).  Indices are clamped into the L x L matrix: a
+                // clamped t only meets zero data (t >= t0 + TC is zero-padded in
+                // LDS) and a clamped projection l >= r is never stored.
                 TIn cf[NCH][4][RL];
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     const int lb = lp + (wave + 4 * c) * RL;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
+                    for (int i = 0; i < 4; ++i) {
+                        const int t = min(tb + i, L - 1);
 #pragma unroll
-                        for (int q = 0; q < RL; ++q)
-                            cf[c][i][q] = (tb + i < t0 + TC && lb + q < r) ? coef[(int64_t)(tb + i) * L + lb + q]
-                                                                           : (TIn)0;
+                        for (int q = 0; q < RL; ++q) cf[c][i][q] = coefc[(int64_t)t * L + min(lb + q, L - 1)];
+                    }
                 }
 #pragma unroll
                 for (int e = 0; e < Ec; ++e) {
