@@ -27,7 +27,7 @@ __all__ = [
     "project_a", "project_b", "gemm_proj", "gemm_proj_block", "gemm_proj_grad",
     "gemm_proj_closed", "gemm_proj_brute", "q_matrix", "blockdiag", "gemm_proj_grad_block",
     "project_signal", "project_kernel", "xcorr_proj", "xcorr_proj_at",
-    "xcorr_proj_closed", "xcorr_proj_sliding", "xcorr_proj_block_rate", "xcorr_proj_block_rate_at",
+    "xcorr_proj_closed", "xcorr_proj_sliding", "xcorr_proj_block_rate", "xcorr_proj_block_rate_at", "xcorr_proj_circular",
     "block_moments", "block_moments_brute", "basis_klt", "pca2d",
     "rel_fro", "snr_db", "work_gemm_plain", "work_gemm_proj",
     "work_conv_plain_time", "work_conv_proj_time",
@@ -402,6 +402,24 @@ def xcorr_proj_sliding(s, k, C, D, r: int) -> np.ndarray:
     kt = (kp.reshape(nb, L) @ q_matrix(C, D, r).T).reshape(-1)
     sp = np.zeros(s.size + nb * L - k.size); sp[:s.size] = s
     return np.correlate(sp, kt, mode="valid")[: s.size - k.size + 1]
+
+
+def xcorr_proj_circular(s, k, C, D, r: int) -> np.ndarray:
+    """Projected circular cross-correlation (Sec. II-B eq. (4): the signal is
+    periodic with period W; Sec. III-A: cyclic translations).  W must be a
+    multiple of L so that the aligned L-blocks of the periodic signal repeat;
+    every block of s is replaced by its reconstruction from the first r
+    projections (s_tilde, as in the linear case) and
+        y[m] = sum_{n<N} k[n] s_tilde[(m + n) mod W],  m = 0 .. W - 1,
+    i.e. the valid cross-correlation of s_tilde extended periodically by N - 1
+    samples (numpy.correlate as one step)."""
+    s, k = _f64(s), _f64(k)
+    L = _f64(C).shape[0]
+    W, N = s.size, k.size
+    assert W % L == 0 and 1 <= N <= W
+    st = (s.reshape(W // L, L) @ q_matrix(C, D, r)).reshape(-1)
+    ext = np.concatenate([st, st[:N - 1]])
+    return np.correlate(ext, k, mode="valid")
 
 
 def _interpolate_block_rate(yd, m, L: int) -> np.ndarray:

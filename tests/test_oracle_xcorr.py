@@ -176,3 +176,42 @@ def test_block_rate_sampled_equals_full():
     full = oracle.xcorr_proj_block_rate(s, k, C, D, 3)
     ms = np.array([0, 1, 7, 8, 9, 200, 433, 437, 440])
     np.testing.assert_allclose(oracle.xcorr_proj_block_rate_at(s, k, C, D, 3, ms), full[ms], rtol=0, atol=0)
+
+
+# ---- circular mode ----------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,L", [("dct2", 4), ("haar", 8), ("identity", 1), ("dct2", 16)])
+@pytest.mark.parametrize("W,N", [(64, 5), (128, 128), (48, 1)])
+def test_circular_all_projections_is_fft_circular_xcorr(kind, L, W, N):
+    """r = L: the exact circular cross-correlation, computed independently in
+    the frequency domain (numpy.fft): y = ifft(fft(s) conj(fft(k_padded)))."""
+    if W % L:
+        pytest.skip("W must be a multiple of L")
+    C, D = oracle.basis(kind, L)
+    s, k = _rand(W, 20), _rand(N, 21)
+    kp = np.zeros(W); kp[:N] = k
+    ref = np.real(np.fft.ifft(np.fft.fft(s) * np.conj(np.fft.fft(kp))))
+    np.testing.assert_allclose(oracle.xcorr_proj_circular(s, k, C, D, L), ref, rtol=1e-9, atol=1e-9)
+
+
+def test_circular_brute_force_every_r():
+    """Pure loops over the definition with explicit modular indices, on the
+    block-projected signal built from the explicit projector Q_r."""
+    L, W, N = 4, 24, 7
+    C, D = oracle.basis("dct2", L)
+    s, k = _rand(W, 22), _rand(N, 23)
+    for r in range(1, L + 1):
+        Q = oracle.q_matrix(C, D, r)
+        st = [sum(s[b * L + t] * Q[t, u] for t in range(L)) for b in range(W // L) for u in range(L)]
+        ref = [sum(k[n] * st[(m + n) % W] for n in range(N)) for m in range(W)]
+        np.testing.assert_allclose(oracle.xcorr_proj_circular(s, k, C, D, r), ref, rtol=1e-10, atol=1e-10)
+
+
+def test_circular_agrees_with_linear_away_from_the_wrap():
+    """The first W - N + 1 outputs do not wrap: they equal the linear
+    projected cross-correlation."""
+    C, D = oracle.basis("dct2", 8)
+    s, k = _rand(256, 24), _rand(40, 25)
+    for r in (1, 3, 8):
+        np.testing.assert_allclose(oracle.xcorr_proj_circular(s, k, C, D, r)[:256 - 40 + 1],
+                                   oracle.xcorr_proj(s, k, C, D, r), rtol=1e-10, atol=1e-10)
