@@ -360,6 +360,20 @@ def main():
                     ent["rel_err_vs_fp64_projected"] = f3(oracle.rel_fro(got, proj))
                 res["full_rate" if rate == "full" else "block_rate"].append(ent)
                 del ws
+        # circular mode on the same signal (period 2^22), N = 16384
+        res["circular"] = []
+        k, _ = inputs.excerpt_kernel(s, 16384, seed=inputs.SEED_KERNEL)
+        kd = torch.from_numpy(k.astype(np.float32)).to(dev)
+        yc = torch.empty(Wc, dtype=torch.float32, device=dev)
+        for rr in (16, 64, 256):
+            ws = torch.empty(lib_ws := pg.lib().pj_conv1d_circular_workspace_bytes(Wc, 16384, Lc, rr, 1),
+                             dtype=torch.uint8, device=dev)
+            fn = lambda: pg.conv1d_circular(sd, kd, rr, bc, out=yc, workspace=ws)
+            t = autotune._time_ms(fn, 10, warmup=3)
+            res["circular"].append({"N": 16384, "L": Lc, "r": rr, "ms": round(t, 5),
+                                    "exact_equiv_tflops": round(2.0 * Wc * 16384 / (t * 1e-3) / 1e12, 3),
+                                    "workspace_bytes": int(lib_ws)})
+            del ws
         # the paper's CONV operating points: a block of 20000 samples, kernels
         # of 600 and 1200 samples, L = 2 Haar, one projection at half or full
         # sampling rate, and the exact result (both projections) for reference

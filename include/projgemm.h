@@ -267,6 +267,25 @@ size_t pj_conv1d_rate_workspace_bytes(int64_t W, int N, int L, int r, int rate, 
 int proj_conv1d_rate(pj_basis b, int r, int mode, int rate, int64_t W, const float* s, int N, const float* k,
                      float* y, int prec, void* ws, size_t ws_bytes, void* stream);
 
+/* Bytes of workspace proj_conv1d_circular needs (0 for invalid arguments). */
+size_t pj_conv1d_circular_workspace_bytes(int64_t W, int N, int L, int r, int prec);
+
+/* Circular cross-correlation (PJ_XCORR) or convolution (PJ_CONV) of the
+ * periodic signal s (period W) with the kernel k (N samples, 1 <= N <= W),
+ * computed on the first r projections (paper Sec. II-B eq. (4); Sec. III-A,
+ * cyclic translations of the input):
+ *   XCORR: y[m] = sum_{n<N} k[n]     s_r[(m + n) mod W],  m = 0 .. W - 1
+ *   CONV : y[m] = sum_{n<N} k[N-1-n] s_r[(m + n) mod W]
+ * with s_r the signal whose aligned L-blocks are replaced by their
+ * reconstruction from the first r projections (as in proj_conv1d).  W must be
+ * a multiple of L (the block grid of a periodic signal repeats only then).
+ *   s, k : device float arrays; y : device float array of W elements.
+ *   prec : PJ_F32.
+ * Errors as proj_conv1d; W not a multiple of L gives PJ_ERR_SHAPE.
+ * Requires ws_bytes >= pj_conv1d_circular_workspace_bytes(...). */
+int proj_conv1d_circular(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k, float* y,
+                         int prec, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- data-adaptive (Karhunen-Loeve) basis ------------------------------------
  * The paper uses fixed bases (DCT-II, Haar) and names projection coefficients
  * derived offline from training data by principal component analysis as the

@@ -741,6 +741,38 @@ int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, c
     return launch_conv(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
 }
 
+size_t pj_conv1d_circular_workspace_bytes(int64_t W, int N, int L, int r, int prec)
+{
+    if (W < 1 || N < 1 || N > W || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec) || W % L != 0) return 0;
+    return (size_t)conv_geom(W + N - 1, N, L, r).total;
+}
+
+int proj_conv1d_circular(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k, float* y,
+                         int prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!b || !s || !k || !y) return PJ_ERR_ARG;
+    if (r < 1 || r > b->L) return PJ_ERR_ARG;
+    if (mode != PJ_XCORR && mode != PJ_CONV) return PJ_ERR_ARG;
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    if (W < 1 || N < 1 || N > W || W % b->L != 0) return PJ_ERR_SHAPE;
+    if (prec != PJ_F32) return PJ_ERR_UNSUPPORTED;
+    const int64_t Wv = W + N - 1;
+    const ConvGeom g = conv_geom(Wv, N, b->L, r);
+    if (g.tiles_m * g.tiles_n > 0x7fffffff || g.k_nrb * g.k_nkb * 64 / 256 > 0x7fffffff || cdiv(g.nout, 256) > 0x7fffffff ||
+        cdiv(g.nbp, 64) > 0x7fffffff || g.ncp * b->L > 0x7fffffff || cdiv((int64_t)r * g.nbp, 256) > 0x7fffffff)
+        return PJ_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < (size_t)g.total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    ConvArgs a;
+    a.s = s; a.W = Wv; a.k = k; a.N = N;
+    a.reverse = (mode == PJ_CONV);
+    a.L = b->L; a.r = r;
+    a.C = b->Cf; a.DT = b->DTf;
+    a.y = y; a.ws = ws;
+    a.period = W;
+    return launch_conv(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
+}
+
 size_t pj_conv1d_rate_workspace_bytes(int64_t W, int N, int L, int r, int rate, int prec)
 {
     if (rate == PJ_RATE_FULL) return pj_conv1d_workspace_bytes(W, N, L, r, prec);

@@ -29,6 +29,8 @@ struct ConvArgs {
     const float* DT;      // D^T[u][l] = D[l][u]
     float* y;
     void* ws;
+    int64_t period = 0;   // > 0: s is periodic with this period (a multiple of L); W is then the
+                          // length of the periodic extension that the outputs read
 };
 int launch_conv(const ConvArgs& a, hipStream_t s);
 

@@ -339,6 +339,17 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
             }
 }
 
+// Circular mode: the projected blocks of a periodic signal repeat, so the
+// rows are completed by copying: sc_l[i] = sc_l[i mod nb0] for nb0 <= i < nbp.
+__global__ __launch_bounds__(256) void wrap_kernel(float* __restrict__ sc, int64_t nbp, int64_t nb0, int r)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t span = nbp - nb0;
+    if (e >= (int64_t)r * span) return;
+    const int64_t l = e / span, i = nb0 + e % span;
+    sc[l * nbp + i] = sc[l * nbp + i % nb0];
+}
+
 // Sum of the split partials, highest projection range first.
 __global__ __launch_bounds__(256) void split_sum_kernel(const float* __restrict__ part, int nsplit, int64_t nout,
                                                         float* __restrict__ y)
@@ -457,7 +468,20 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
     float* sc = (float*)a.ws;
     char* kp = (char*)a.ws + g.sc_bytes;
     // step 1
-    if (launch_sig_project(a, sc, g.nbp, st) != 0) return -1;
+    if (a.period > 0) {
+        // periodic signal: project its W / L blocks once, then repeat them
+        ConvArgs p = a;
+        p.W = a.period;
+        const int64_t nb0 = a.period / a.L;
+        if (launch_sig_project(p, sc, g.nbp, st) != 0) return -1;
+        const int64_t n = (int64_t)a.r * (g.nbp - nb0);
+        if (n > 0) {
+            hipLaunchKernelGGL(wrap_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, sc, g.nbp, nb0, a.r);
+            if (hipGetLastError() != hipSuccess) return -1;
+        }
+    } else if (launch_sig_project(a, sc, g.nbp, st) != 0) {
+        return -1;
+    }
     // step 2
     {
         if (a.L % 32 != 0) {

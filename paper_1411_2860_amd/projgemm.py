@@ -71,6 +71,8 @@ _SIGNATURES = {
                                 _i64, _i, _vp, _sz, _vp]),
     "proj_conv1d": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
     "pj_conv1d_rate_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i, _i]),
+    "pj_conv1d_circular_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i]),
+    "proj_conv1d_circular": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
     "pj_block_moments_workspace_bytes": (_sz, [_i64, _i64, _i]),
     "pj_block_moments": (_i, [_i, _i64, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
     "pj_basis_create_klt": (_i, [ctypes.POINTER(_vp), _i, _dp, _dp]),
@@ -352,6 +354,27 @@ def conv1d(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, works
     _check(lib().proj_conv1d_rate(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], _RATES[rate], Wn, _ptr(s), N,
                                   _ptr(k), _ptr(out), _prec(prec), _ptr(workspace), workspace.numel(),
                                   _stream(stream)), "proj_conv1d_rate")
+    return out
+
+
+def conv1d_circular(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, workspace=None, stream=None):
+    """Projected circular cross-correlation / convolution of the periodic
+    float32 CUDA signal s (period W, a multiple of L) with k (N <= W): W
+    outputs (proj_conv1d_circular)."""
+    import torch
+    Wn, N = s.numel(), k.numel()
+    if s.dtype != torch.float32 or k.dtype != torch.float32:
+        raise TypeError("s and k must be float32")
+    if not (s.is_contiguous() and k.is_contiguous()):
+        raise ValueError("s and k must be contiguous")
+    if out is None:
+        out = torch.empty(Wn, dtype=torch.float32, device=s.device)
+    if workspace is None:
+        workspace = _byte_buffer(int(lib().pj_conv1d_circular_workspace_bytes(Wn, N, basis.L, r, _prec(prec))),
+                                 s.device)
+    _check(lib().proj_conv1d_circular(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], Wn, _ptr(s), N, _ptr(k),
+                                      _ptr(out), _prec(prec), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "proj_conv1d_circular")
     return out
 
 

@@ -270,3 +270,24 @@ def test_klt_and_moments_validation(lib):
     assert lib.pj_block_moments(64, 0, 4096, FAKE, 4096, FAKE, FAKE, n, None) == SHAPE
     assert lib.pj_block_moments(64, 1000, 4096, FAKE, 4096, FAKE, FAKE, n - 1, None) == WS
     assert lib.pj_block_moments(64, 1000, 4096, FAKE, 4096, FAKE, FAKE, n, None) == HIP
+
+
+def test_conv_circular_validation(lib, basis16):
+    W, N = 1024, 37
+    n = lib.pj_conv1d_circular_workspace_bytes(W, N, 16, 4, 1)
+    assert n > 0
+    assert lib.pj_conv1d_circular_workspace_bytes(1000, N, 16, 4, 1) == 0      # W not a multiple of L
+    assert lib.pj_conv1d_circular_workspace_bytes(W, W + 1, 16, 4, 1) == 0
+    b = basis16
+    call = lambda **kw: lib.proj_conv1d_circular(kw.get("h", b.handle), kw.get("r", 4), kw.get("mode", 0),
+                                                 kw.get("W", W), FAKE, kw.get("N", N), FAKE, FAKE, kw.get("prec", 1),
+                                                 FAKE, kw.get("ws", n), None)
+    assert call(h=None) == ARG
+    assert call(r=0) == ARG
+    assert call(mode=3) == ARG
+    assert call(W=1000) == SHAPE
+    assert call(N=W + 1) == SHAPE
+    assert call(N=0) == SHAPE
+    assert call(prec=0) == UNSUP
+    assert call(ws=n - 1) == WS
+    assert call() == HIP

@@ -211,3 +211,65 @@ def test_block_rate_full_size_sampled(pg, long_signal, r):
     ref = oracle.xcorr_proj_block_rate_at(s, k, C, D, r, ms)
     mag = oracle.xcorr_proj_block_rate_at(np.abs(s), np.abs(k), np.abs(C), np.abs(D), r, ms)
     _tol.assert_within(got, ref, block_bound(256, r, N, mag), f"block full size r={r}")
+
+
+# ---- circular mode -----------------------------------------------------------------
+
+def _check_circular(pg, s, k, kind, L, r, mode="xcorr"):
+    basis = pg.Basis(kind, L)
+    C, D = basis.matrices()
+    y = pg.conv1d_circular(_dev(s), _dev(k), r, basis, mode=mode)
+    torch.cuda.synchronize()
+    got = y.double().cpu().numpy()
+    kk = k[::-1] if mode == "conv" else k
+    ref = oracle.xcorr_proj_circular(s, kk, C, D, r)
+    mag = oracle.xcorr_proj_circular(np.abs(s), np.abs(kk), np.abs(C), np.abs(D), r)
+    _tol.assert_within(got, ref, conv_bound(L, r, k.size, mag), f"circular {kind} L={L} r={r} N={k.size} {mode}")
+    return got, ref
+
+
+@pytest.mark.parametrize("W,N,L,kind", [
+    (4096, 300, 16, "dct2"),
+    (4096, 4096, 16, "haar"),     # N = W: every output wraps
+    (1024, 1, 8, "dct2"),
+    (768, 100, 1, "identity"),    # L = 1: exact circular cross-correlation
+    (65536, 2000, 256, "dct2"),
+    (700, 33, 5, "dct2"),         # L not a power of two
+])
+def test_circular(pg, W, N, L, kind):
+    s = inputs.ar2_signal(W, seed=31)
+    k, _ = inputs.excerpt_kernel(s, N, seed=32)
+    for r in sorted({1, max(1, L // 3), L}):
+        got, _ = _check_circular(pg, s, k, kind, L, r)
+        if r == L:
+            kp = np.zeros(W); kp[:N] = k
+            exact = np.real(np.fft.ifft(np.fft.fft(s) * np.conj(np.fft.fft(kp))))
+            assert oracle.rel_fro(got, exact) < 1e-5
+
+
+def test_circular_convolution_mode(pg):
+    s = inputs.ar2_signal(2048, seed=33)
+    k, _ = inputs.excerpt_kernel(s, 150, seed=34)
+    _check_circular(pg, s, k, "dct2", 8, 3, mode="conv")
+
+
+@pytest.mark.parametrize("r", [16, 256])
+def test_circular_full_size_sampled(pg, long_signal, r):
+    """2^22 samples, N = 16384, L = 256: sampled outputs on both sides of
+    the wrap against the linear oracle run on the periodic extension (padded
+    to whole blocks, so every block is a copy of one of the signal's)."""
+    s = long_signal
+    N, L, W = 16384, 256, s.size
+    k, _ = inputs.excerpt_kernel(s, N, seed=inputs.SEED_KERNEL)
+    basis = pg.Basis("dct2", L)
+    C, D = basis.matrices()
+    y = pg.conv1d_circular(_dev(s), _dev(k), r, basis)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(r + 11)
+    ms = np.unique(np.concatenate([[0, W - N, W - N + 1, W - 1], rng.integers(0, W, 100),
+                                   rng.integers(W - N, W, 100)]))
+    got = y[torch.from_numpy(ms).cuda()].double().cpu().numpy()
+    ext = np.concatenate([s, s[:-(-(N - 1) // L) * L]])
+    ref = oracle.xcorr_proj_at(ext, k, C, D, r, ms)
+    mag = oracle.xcorr_proj_at(np.abs(ext), np.abs(k), np.abs(C), np.abs(D), r, ms)
+    _tol.assert_within(got, ref, conv_bound(L, r, N, mag), f"circular full size r={r}")
