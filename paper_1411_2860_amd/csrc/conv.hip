@@ -350,6 +350,54 @@ __global__ __launch_bounds__(256) void wrap_kernel(float* __restrict__ sc, int64
     sc[l * nbp + i] = sc[l * nbp + i % nb0];
 }
 
+// ---- short blocks (L <= kSmallL): vector-ALU path ----------------------------
+// With a handful of phases a 32-phase matrix-core tile would be mostly
+// padding; the phases are then kept in a plain layout
+//     kd[b][l][c] = kd_l[cL - b] = sum_u D[l, u] k'(cL - b + u)
+// and each output is one thread's dot products over the projections.
+constexpr int kSmallL = 8;
+
+__global__ __launch_bounds__(256) void kphase_plain_kernel(const float* __restrict__ k, int64_t N, int reverse, int L,
+                                                           int r, int64_t nc, const float* __restrict__ DT,
+                                                           float* __restrict__ kd)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;     // (b * r + l) * nc + c
+    if (idx >= (int64_t)L * r * nc) return;
+    const int64_t c = idx % nc;
+    const int l = (int)((idx / nc) % r);
+    const int b = (int)(idx / (nc * r));
+    float acc = 0.0f;
+    for (int u = 0; u < L; ++u) {
+        const int64_t n = c * L - b + u;
+        float kv = 0.0f;
+        if (n >= 0 && n < N) kv = reverse ? k[N - 1 - n] : k[n];
+        acc += DT[(int64_t)u * L + l] * kv;
+    }
+    kd[idx] = acc;
+}
+
+// y[aL + b] = sum_l sum_{c < nc} sc_l[a + c] kd[b][l][c], highest projection
+// first with one partial sum per projection.
+__global__ __launch_bounds__(256) void xcorr_small_kernel(const float* __restrict__ sc, int64_t nbp,
+                                                          const float* __restrict__ kd, int64_t nc, int L, int r,
+                                                          int64_t nout, float* __restrict__ y)
+{
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= nout) return;
+    const int64_t a = m / L;
+    const int b = (int)(m - a * L);
+    float tot = 0.0f;
+    for (int l = r - 1; l >= 0; --l) {
+        const float* sp = sc + (int64_t)l * nbp + a;
+        const float* kp = kd + ((int64_t)b * r + l) * nc;
+        float part = 0.0f;
+#pragma unroll 8
+        for (int64_t c = 0; c < nc; ++c) part += sp[c] * kp[c];
+        tot += part;
+    }
+    y[m] = tot;
+}
+
 // Sum of the split partials, highest projection range first.
 __global__ __launch_bounds__(256) void split_sum_kernel(const float* __restrict__ part, int nsplit, int64_t nout,
                                                         float* __restrict__ y)
@@ -437,13 +485,14 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
     g.k_nkb = (int64_t)r * g.ncp / 8;
     const int bnb = L > 128 ? 8 : 4;
     g.tiles_n = cdiv(g.k_nrb, bnb);
+    g.small = L <= kSmallL;
     const int64_t tiles = g.tiles_m * g.tiles_n;
     int64_t ns = std::max<int64_t>(1, kXcorrTargetWG / std::max<int64_t>(1, tiles));
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, g.k_nkb / kXcorrMinSteps));
     ns = std::min<int64_t>(ns, r);
-    g.nsplit = (int)ns;
+    g.nsplit = g.small ? 1 : (int)ns;
     g.sc_bytes = rup((int64_t)r * g.nbp * 4, 256);
-    g.k_bytes = g.k_nrb * g.k_nkb * 1024;
+    g.k_bytes = g.small ? rup((int64_t)L * r * g.nc * 4, 256) : g.k_nrb * g.k_nkb * 1024;
     g.part_bytes = g.nsplit > 1 ? rup((int64_t)g.nsplit * g.nout * 4, 256) : 0;
     g.total = g.sc_bytes + g.k_bytes + g.part_bytes;
     return g;
@@ -481,6 +530,16 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
         }
     } else if (launch_sig_project(a, sc, g.nbp, st) != 0) {
         return -1;
+    }
+    if (g.small) {
+        float* kd = (float*)kp;
+        const int64_t nk = (int64_t)a.L * a.r * g.nc;
+        hipLaunchKernelGGL(kphase_plain_kernel, dim3((unsigned)cdiv(nk, 256)), dim3(256), 0, st, a.k, a.N, a.reverse,
+                           a.L, a.r, g.nc, a.DT, kd);
+        if (hipGetLastError() != hipSuccess) return -1;
+        hipLaunchKernelGGL(xcorr_small_kernel, dim3((unsigned)cdiv(g.nout, 256)), dim3(256), 0, st, sc, g.nbp, kd,
+                           g.nc, a.L, a.r, g.nout, a.y);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     // step 2
     {
