@@ -328,13 +328,15 @@ __device__ __forceinline__ void gemm_tile_lds(
             }
         }
     }
-    f32x4 stage[PER_T];
-    auto gload = [&](int64_t kb) {
+    // two register sets: the loads of step st + 2 are issued while step st is
+    // contracted, so each global load has two k-blocks of work to hide behind
+    f32x4 stage0[PER_T], stage1[PER_T];
+    auto gload = [&](int64_t kb, f32x4 (&stage)[PER_T]) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i)
             stage[i] = ok[i] ? *reinterpret_cast<const f32x4*>(src[i] + kb * 1024) : f32x4{0.f, 0.f, 0.f, 0.f};
     };
-    auto swrite = [&](int s) {
+    auto swrite = [&](int s, const f32x4 (&stage)[PER_T]) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
             const int c = tid + i * NT;
@@ -350,15 +352,8 @@ __device__ __forceinline__ void gemm_tile_lds(
 #pragma unroll
             for (int j = 0; j < T::NACC; ++j) acc[a][b][j] = 0;
 
-    // highest projection first (see gemm_tile)
-    if (nkb > 0) {
-        gload(nkb - 1);
-        swrite(0);
-    }
-    __syncthreads();
-    for (int64_t st = 0; st < nkb; ++st) {
-        const int s = (int)(st & 1);
-        if (st + 1 < nkb) gload(nkb - 2 - st);
+    // highest projection first (see gemm_tile): step st contracts k-block nkb - 1 - st
+    auto contract = [&](int s) {
         frag fa[WM][PL], fb[WN][PL];
 #pragma unroll
         for (int a = 0; a < WM; ++a)
@@ -374,8 +369,25 @@ __device__ __forceinline__ void gemm_tile_lds(
         for (int a = 0; a < WM; ++a)
 #pragma unroll
             for (int b = 0; b < WN; ++b) T::mma(acc[a][b], fa[a], fb[b]);
-        if (st + 1 < nkb) swrite(s ^ 1);
+    };
+    // step st (LDS buffer st & 1): issue the loads of step st + 2 into the
+    // register set that held step st, contract, then park step st + 1 (the
+    // other register set) in the other LDS buffer
+    auto step = [&](int64_t st, f32x4 (&ld_set)[PER_T], const f32x4 (&st_set)[PER_T]) {
+        if (st + 2 < nkb) gload(nkb - 3 - st, ld_set);
+        contract((int)(st & 1));
+        if (st + 1 < nkb) swrite((int)((st + 1) & 1), st_set);
         __syncthreads();
+    };
+    if (nkb > 0) {
+        gload(nkb - 1, stage0);
+        swrite(0, stage0);
+    }
+    if (nkb > 1) gload(nkb - 2, stage1);
+    __syncthreads();
+    for (int64_t st = 0; st < nkb; st += 2) {
+        step(st, stage0, stage1);
+        if (st + 1 < nkb) step(st + 1, stage1, stage0);
     }
 
     const int64_t rb0 = rbB + wm * WM, cb0 = cbB + wn * WN;
@@ -574,7 +586,7 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
     if (prec == P_F64) return 10;                                  // LDS, 8 waves, 128 x 64 (16 x 16 blocks)
     if (prec == P_FP8) return 0;
     if (prec == P_FP8X2) return 5;
-    if (prec == P_BF16X3 || prec == P_F16X3) return 10;            // LDS 256 x 128, 8 waves
+    if (prec == P_BF16X3 || prec == P_F16X3 || prec == P_F32) return 10;   // LDS 256 x 128, 8 waves
     return 6;                                                      // LDS 128 x 128
 }
 
