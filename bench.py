@@ -39,7 +39,7 @@ PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500
 MFMA_PER_PRODUCT = {"bf16x3": 3, "f16x3": 3, "fp8x2": 3}
 PEAK_HBM = 8000.0                            # GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f32_recognition_traffic.md")
-SECTIONS = ["sweep", "precisions", "plain", "klt", "pca2d", "conv", "batched", "mlp"]
+SECTIONS = ["sweep", "precisions", "plain", "static_database", "klt", "pca2d", "conv", "batched", "mlp"]
 
 
 def log(msg):
@@ -247,6 +247,30 @@ def main():
                         "rel_err_vs_fp64_exact": f3(e1), "rel_err_vs_fp64_projected": f3(e2)})
             del R_p
         return res
+
+    def sec_static_database():
+        # the database (8192 images) packed once at r = 64 (a projection-major
+        # pack serves every r <= 64); each step projects the 1024 queries and
+        # contracts -- the deployment where the database is static
+        Bp64 = pg.pack_b(Bd, 64, basis, prec="f32", transB=True)
+        torch.cuda.synchronize()
+        out = []
+        for rr in (1, 4, 8, 16, 64):
+            cfg_s = autotune.tune_gemm(M, W, K, L, rr, "f32", reps=3, basis=basis)
+            Ap = torch.empty(pg.packed_bytes(M, K, L, rr, "f32"), dtype=torch.uint8, device=dev)
+            R_s = torch.empty((M, W), dtype=torch.float32, device=dev)
+
+            def st():
+                pg.pack_a(Ad, rr, basis, prec="f32", out=Ap)
+                pg.gemm_packed(Ap, Bp64, rr, M, W, K, L, rr, 64, prec="f32", out=R_s, tile_cfg=cfg_s)
+            t = autotune._time_ms(st, args.steps, warmup=args.warmup)
+            e_exact, e_proj, _ = sampled_errors(rr, R_s)
+            out.append({"r": rr, "ms_per_step": round(t, 5), "tile_cfg": cfg_s,
+                        "exact_equiv_tflops": round(exact_flops / (t * 1e-3) / 1e12, 3),
+                        "rel_err_vs_fp64_exact": f3(e_exact), "rel_err_vs_fp64_projected": f3(e_proj)})
+            del R_s, Ap
+        del Bp64
+        return out
 
     def sec_klt():
         # data-adaptive basis: block second moments of 2048 database images on
@@ -479,6 +503,7 @@ def main():
     section("sweep", sec_sweep)
     section("precisions", sec_precisions)
     section("plain", sec_plain)
+    section("static_database", sec_static_database)
     section("klt", sec_klt)
     section("pca2d", sec_pca2d)
     section("conv", sec_conv)
