@@ -67,9 +67,9 @@ def cpu_baseline(A, Bt, r):
         t0 = time.perf_counter()
         oracle.gemm_proj_block(A, Bk, C, D, r, np.arange(n), cols)
         return time.perf_counter() - t0
-    t8, t40 = run(8), run(40)
-    per_row = max((t40 - t8) / 32.0, 1e-4)
-    rows = int((15.0 - t8) / per_row) if t8 < 15.0 else 8
+    t8, t40 = run(16), run(144)      # the B projection is a fixed cost: two sizes separate it
+    per_row = max((t40 - t8) / 128.0, 1e-4)
+    rows = int((15.0 - t8) / per_row) + 16 if t8 < 15.0 else 16
     rows = min(M, max(8, rows // 8 * 8))
     t = run(rows)
     return {"value": round(2.0 * rows * K * W / t / 1e12, 6), "unit": "exact-equivalent TFLOP/s",

@@ -67,7 +67,6 @@ void make_haar(int L, std::vector<double>& C)
     }
 }
 
-// D = C^{-1} by LU with partial pivoting; false if C is (numerically) singular.
 // Eigen-decomposition of a symmetric L x L matrix by cyclic Jacobi rotations
 // in FP64: on return A is (numerically) diagonal with the eigenvalues and the
 // columns of V are the eigenvectors.  Each rotation J in the (p, q) plane
@@ -112,6 +111,7 @@ void jacobi_eig(int L, std::vector<double>& A, std::vector<double>& V)
     }
 }
 
+// D = C^{-1} by LU with partial pivoting; false if C is (numerically) singular.
 bool invert_lu(int L, const std::vector<double>& C, std::vector<double>& D)
 {
     std::vector<double> a(C);
@@ -348,11 +348,22 @@ size_t pj_packed_bytes(int rows, int K, int L, int rmax, int prec)
     return (size_t)pack_geom(rows, K, L, rmax, prec).total;
 }
 
+// Bytes of the k-range partials proj_gemm uses for a skinny output (0 if the
+// contraction is not split).
+static size_t gemm_split_bytes(int M, int W, int K, int L, int r, int prec)
+{
+    const PackGeom g = pack_geom(M, K, L, r, prec);
+    const int64_t nkb = (int64_t)r * g.Gp / layout_of(prec).KB;
+    const int ns = gemm_split_count(prec, M, W, nkb, -1);
+    if (ns <= 1) return 0;
+    return align256((size_t)ns * M * W * (prec == PJ_F64 ? 8 : 4));
+}
+
 size_t pj_gemm_workspace_bytes(int M, int W, int K, int L, int r, int prec)
 {
     size_t a = pj_packed_bytes(M, K, L, r, prec), b = pj_packed_bytes(W, K, L, r, prec);
     if (!a || !b) return 0;
-    return align256(a) + align256(b);
+    return align256(a) + align256(b) + gemm_split_bytes(M, W, K, L, r, prec);
 }
 
 int pj_pack_a(pj_basis b, int rmax, char transA, int M, int K, const void* A, int64_t lda, int prec,
@@ -402,9 +413,22 @@ int pj_pack_ab(pj_basis b, int rmax, char transA, char transB, int M, int W, int
     return run_pack(prec, pa, 2, stream);
 }
 
+// pj_gemm_packed with optional k-range partials (nsplit > 1 needs `part`).
+static int gemm_packed_impl(int r, int M, int W, int K, int L, int prec, const void* Ap, int rmax_a,
+                            size_t a_bytes, const void* Bp, int rmax_b, size_t b_bytes, float beta, void* R,
+                            int64_t ldr, int tile_cfg, int nsplit, void* part, void* stream);
+
 int pj_gemm_packed(int r, int M, int W, int K, int L, int prec, const void* Ap, int rmax_a, size_t a_bytes,
                    const void* Bp, int rmax_b, size_t b_bytes, float beta, void* R, int64_t ldr, int tile_cfg,
                    void* stream)
+{
+    return gemm_packed_impl(r, M, W, K, L, prec, Ap, rmax_a, a_bytes, Bp, rmax_b, b_bytes, beta, R, ldr, tile_cfg, 1,
+                            nullptr, stream);
+}
+
+static int gemm_packed_impl(int r, int M, int W, int K, int L, int prec, const void* Ap, int rmax_a,
+                            size_t a_bytes, const void* Bp, int rmax_b, size_t b_bytes, float beta, void* R,
+                            int64_t ldr, int tile_cfg, int nsplit, void* part, void* stream)
 {
     if (!Ap || !Bp || !R) return PJ_ERR_ARG;
     if (!valid_prec(prec)) return PJ_ERR_ARG;
@@ -428,6 +452,8 @@ int pj_gemm_packed(int r, int M, int W, int K, int L, int prec, const void* Ap, 
     g.R = R;
     g.ldr = ldr;
     g.beta = beta;
+    g.nsplit = part ? nsplit : 1;
+    g.part = part;
     if (tile_cfg >= gemm_num_configs()) return PJ_ERR_ARG;
     int rc = launch_gemm(prec, g, tile_cfg, (hipStream_t)stream);
     return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
@@ -452,12 +478,18 @@ int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, 
     if (!b->on_device) return PJ_ERR_HIP;
     char* wa = (char*)ws;
     char* wb = wa + align256(pj_packed_bytes(M, K, b->L, r, prec));
+    char* wp = wb + align256(pj_packed_bytes(W, K, b->L, r, prec));
     PackArgs pa[2] = {pack_args(b, r, true, transA, M, K, A, lda, prec, wa),
                       pack_args(b, r, false, transB, W, K, B, ldb, prec, wb)};
     int rc = run_pack(prec, pa, 2, stream);
     if (rc != PJ_OK) return rc;
-    return pj_gemm_packed(r, M, W, K, b->L, prec, wa, r, pj_packed_bytes(M, K, b->L, r, prec), wb, r,
-                          pj_packed_bytes(W, K, b->L, r, prec), beta, R, ldr, -1, stream);
+    const PackGeom ga = pack_geom(M, K, b->L, r, prec);
+    const int ns = gemm_split_bytes(M, W, K, b->L, r, prec) > 0
+                       ? gemm_split_count(prec, M, W, (int64_t)r * ga.Gp / layout_of(prec).KB, -1)
+                       : 1;
+    return gemm_packed_impl(r, M, W, K, b->L, prec, wa, r, pj_packed_bytes(M, K, b->L, r, prec), wb, r,
+                            pj_packed_bytes(W, K, b->L, r, prec), beta, R, ldr, -1, ns, ns > 1 ? wp : nullptr,
+                            stream);
 }
 
 // ---------------------------------------------------------------- batched

@@ -134,6 +134,8 @@ struct GemmArgs {
     int64_t P, Q;
     void* R; int64_t ldr;        // P x Q row-major, float (double for F64)
     float beta;
+    int nsplit = 1;              // > 1: contiguous k-block ranges with partials in `part`
+    void* part = nullptr;        // nsplit x P x Q partials (output type), caller workspace
 };
 // Synthesis with the projection coefficients (the transpose of the pack's
 // projection): out(p, jL + t) = sum_{l<r} in(p, l*Gp + j) coef[t, l].
@@ -167,5 +169,6 @@ int launch_gemm(int prec, const GemmArgs& a, int cfg, hipStream_t s);
 int gemm_num_configs();
 int gemm_config_tile(int prec, int cfg, int* tile_m, int* tile_n);
 int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb);
+int gemm_split_count(int prec, int64_t P, int64_t Q, int64_t nkb, int cfg);
 
 }  // namespace pj

@@ -12,6 +12,8 @@
 // cores work on the current one.  Workgroups are mapped XCD-aware: the
 // hardware deals workgroups round-robin over the 8 XCDs, so consecutive
 // logical tiles are regrouped to land on the same XCD and share its L2.
+#include <algorithm>
+
 #include "common.h"
 
 namespace pj {
@@ -180,7 +182,7 @@ template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 __device__ __forceinline__ void gemm_tile(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
-    int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
+    int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
     float beta, int64_t tm, int64_t tn)
 {
     using T = MT<PREC>;
@@ -199,12 +201,12 @@ __device__ __forceinline__ void gemm_tile(
 #pragma unroll
     for (int a = 0; a < WM; ++a) {
         xv[a] = rb0 + a < x_nrb;
-        xt[a] = (xv[a] ? rb0 + a : 0) * x_nkb;
+        xt[a] = (xv[a] ? rb0 + a : 0) * x_nkb + kb_lo;   // k-blocks kb_lo .. kb_lo + nkb - 1
     }
 #pragma unroll
     for (int b = 0; b < WN; ++b) {
         yv[b] = cb0 + b < y_nrb;
-        yt[b] = (yv[b] ? cb0 + b : 0) * y_nkb;
+        yt[b] = (yv[b] ? cb0 + b : 0) * y_nkb + kb_lo;
     }
 
     acc_t acc[WM][WN];
@@ -282,7 +284,7 @@ template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 __device__ __forceinline__ void gemm_tile_lds(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
-    int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
+    int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
     float beta, int64_t tm, int64_t tn)
 {
     using T = MT<PREC>;
@@ -320,11 +322,11 @@ __device__ __forceinline__ void gemm_tile_lds(
             if (blk < BMB) {
                 const int64_t rb = rbB + blk;
                 ok[i] = rb < x_nrb;
-                src[i] = X + pl * x_plane + ((ok[i] ? rb : 0) * x_nkb * 64 + lc) * 16;
+                src[i] = X + pl * x_plane + (((ok[i] ? rb : 0) * x_nkb + kb_lo) * 64 + lc) * 16;
             } else {
                 const int64_t cb = cbB + blk - BMB;
                 ok[i] = cb < y_nrb;
-                src[i] = Y + pl * y_plane + ((ok[i] ? cb : 0) * y_nkb * 64 + lc) * 16;
+                src[i] = Y + pl * y_plane + (((ok[i] ? cb : 0) * y_nkb + kb_lo) * 64 + lc) * 16;
             }
         }
     }
@@ -414,15 +416,15 @@ template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 __device__ __forceinline__ void gemm_any(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
-    int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
+    int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
     float beta, int64_t tm, int64_t tn)
 {
     if constexpr (KIND == 1 && sizeof(typename MT<PREC>::frag) == 16)
         gemm_tile_lds<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
-                                                      nkb, P, Q, R, ldr, beta, tm, tn);
+                                                      nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
     else
         gemm_tile<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
-                                                  nkb, P, Q, R, ldr, beta, tm, tn);
+                                                  nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
 }
 
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
@@ -446,11 +448,33 @@ __global__ PJ_GEMM_BOUNDS void gemm_kernel(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
     int64_t nkb, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
-    float beta, int64_t tiles_m, int64_t ntiles)
+    float beta, int64_t tiles_m, int64_t ntiles, int nsplit, typename MT<PREC>::out_t* __restrict__ part)
 {
+    // grid.y = contiguous k-block ranges; with more than one, each range
+    // writes its own P x Q partial and gemm_split_sum_kernel adds them
     const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+    const int sp = blockIdx.y;
+    const int64_t lo = nkb * sp / nsplit, hi = nkb * (sp + 1) / nsplit;
+    typename MT<PREC>::out_t* dst = nsplit == 1 ? R : part + (int64_t)sp * P * Q;
     gemm_any<KIND, PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
-                                                   nkb, P, Q, R, ldr, beta, tile % tiles_m, tile / tiles_m);
+                                                   hi - lo, lo, P, Q, dst, nsplit == 1 ? ldr : Q,
+                                                   nsplit == 1 ? beta : 0.0f, tile % tiles_m, tile / tiles_m);
+}
+
+// Sum of the k-range partials, highest range (highest projections) first,
+// then beta R.
+template <typename OT>
+__global__ __launch_bounds__(256) void gemm_split_sum_kernel(const OT* __restrict__ part, int nsplit, int64_t P,
+                                                             int64_t Q, OT* __restrict__ R, int64_t ldr, float beta)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= P * Q) return;
+    const int64_t n = P * Q;
+    OT v = part[(int64_t)(nsplit - 1) * n + e];
+    for (int sp = nsplit - 2; sp >= 0; --sp) v += part[(int64_t)sp * n + e];
+    const int64_t p = e / Q, q = e - p * Q;
+    if (beta != 0.0f) v += (OT)beta * R[p * ldr + q];
+    R[p * ldr + q] = v;
 }
 
 // Persistent grouped launch: workgroup b processes items b, b + grid, ... of
@@ -465,7 +489,7 @@ __global__ PJ_GEMM_BOUNDS void gemm_grouped_kernel(
         const GroupedProblem& p = probs[w.prob];
         gemm_any<KIND, PREC, WM, WN, WAVES_M, WAVES_N>(
             (const char*)p.X, p.x_nrb, p.x_nkb, p.x_plane, p.x_pb, (const char*)p.Y, p.y_nrb, p.y_nkb, p.y_plane,
-            p.y_pb, p.nkb, p.P, p.Q, (typename MT<PREC>::out_t*)p.R, p.ldr, p.beta, w.tm, w.tn);
+            p.y_pb, p.nkb, 0, p.P, p.Q, (typename MT<PREC>::out_t*)p.R, p.ldr, p.beta, w.tm, w.tn);
     }
 }
 
@@ -478,12 +502,20 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     const int64_t ntiles = tiles_m * tiles_n;
     (void)RB;
     constexpr size_t lds = gemm_lds_bytes<KIND, PREC, WM, WN, WAVES_M, WAVES_N>();
-    hipLaunchKernelGGL((gemm_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>), dim3((unsigned)ntiles),
+    using OT = typename MT<PREC>::out_t;
+    const int ns = a.nsplit > 1 && a.part ? a.nsplit : 1;
+    hipLaunchKernelGGL((gemm_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>), dim3((unsigned)ntiles, (unsigned)ns),
                        dim3(64 * WAVES_M * WAVES_N), lds, s,
                        (const char*)a.X, a.gx.nrb, a.gx.nkb, a.gx.plane_bytes + a.gx.scale_plane, a.gx.plane_bytes,
                        (const char*)a.Y, a.gy.nrb, a.gy.nkb, a.gy.plane_bytes + a.gy.scale_plane, a.gy.plane_bytes,
-                       a.nkb, a.P, a.Q, (typename MT<PREC>::out_t*)a.R, a.ldr, a.beta, tiles_m, ntiles);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+                       a.nkb, a.P, a.Q, (OT*)a.R, a.ldr, a.beta, tiles_m, ntiles, ns, (OT*)a.part);
+    if (hipGetLastError() != hipSuccess) return -1;
+    if (ns > 1) {
+        hipLaunchKernelGGL(gemm_split_sum_kernel<OT>, dim3((unsigned)cdiv(a.P * a.Q, 256)), dim3(256), 0, s,
+                           (const OT*)a.part, ns, a.P, a.Q, (OT*)a.R, a.ldr, a.beta);
+        if (hipGetLastError() != hipSuccess) return -1;
+    }
+    return 0;
 }
 
 }  // namespace
@@ -588,6 +620,21 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
     if (prec == P_FP8X2) return 5;
     if (prec == P_BF16X3 || prec == P_F16X3 || prec == P_F32) return 10;   // LDS 256 x 128, 8 waves
     return 6;                                                      // LDS 128 x 128
+}
+
+// Contiguous k-block ranges for a contraction whose tile grid alone would
+// under-fill the chip (skinny outputs with a long contraction: scatter and
+// Gram matrices): about 256 workgroups, at least 32 k-blocks per range.
+int gemm_split_count(int prec, int64_t P, int64_t Q, int64_t nkb, int cfg)
+{
+    if (cfg < 0) cfg = gemm_default_config(prec, P, Q, nkb);
+    int tm = 0, tn = 0;
+    if (gemm_config_tile(prec, cfg, &tm, &tn) != 0) return 1;
+    const int64_t tiles = cdiv(P, tm) * cdiv(Q, tn);
+    if (tiles >= 128 || nkb < 64) return 1;
+    int64_t ns = std::min<int64_t>(cdiv(256, tiles), nkb / 32);
+    ns = std::min<int64_t>(ns, 64);
+    return (int)std::max<int64_t>(ns, 1);
 }
 
 int launch_gemm(int prec, const GemmArgs& a, int cfg, hipStream_t s)

@@ -177,7 +177,7 @@ def test_packed_once_serves_every_r(pg, images):
     Bp = pg.pack_b(Bd, 32, basis, transB=True)
     for r in (1, 7, 32):
         a = pg.gemm_packed(Ap, Bp, r, M, W, K, 64, 32, 32)
-        b = pg.gemm(Ad, Bd, r, basis, transB=True)
+        b = pg.gemm_packed(pg.pack_a(Ad, r, basis), pg.pack_b(Bd, r, basis, transB=True), r, M, W, K, 64, r, r)
         torch.cuda.synchronize()
         assert torch.equal(a, b)
 
@@ -211,3 +211,36 @@ def test_full_size_sampled(pg, full_images, r):
     if r == 64:
         exact = A[rows] @ Bt[cols].T
         assert oracle.rel_fro(got, exact) < 1e-5
+
+
+@pytest.mark.parametrize("prec,r,L,K,beta", [
+    ("f32", 1, 16, 65536, 0.0), ("f32", 16, 16, 65536, 0.0), ("f32", 7, 12, 60001, 0.5),
+    ("bf16x3", 4, 16, 65536, 0.0), ("f16", 8, 8, 32768, 0.0), ("f64", 3, 8, 32768, -1.0), ("fp8", 8, 16, 65536, 0.0),
+])
+def test_skinny_output_split_contraction(pg, prec, r, L, K, beta):
+    """96 x 96 outputs with a long contraction: the k-blocks are cut into
+    contiguous ranges contracted by separate workgroups and summed afterwards
+    (highest range first); every output against the oracle, with beta."""
+    M = W = 96
+    rng = np.random.default_rng(K + r)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, W))
+    R0 = rng.standard_normal((M, W))
+    basis = pg.Basis("dct2", L)
+    C, D = basis.matrices()
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Ad, Bd = torch.from_numpy(A).to(dt).cuda(), torch.from_numpy(B).to(dt).cuda()
+    R = torch.from_numpy(R0).to(dt).cuda()
+    nbytes = pg.gemm_workspace_bytes(M, W, K, L, r, prec)
+    assert nbytes > pg.packed_bytes(M, K, L, r, prec) + pg.packed_bytes(W, K, L, r, prec)   # partials included
+    pg.gemm(Ad, Bd, r, basis, prec=prec, beta=beta, out=R)
+    torch.cuda.synchronize()
+    A32 = A.astype(np.float32).astype(np.float64) if prec != "f64" else A
+    B32 = B.astype(np.float32).astype(np.float64) if prec != "f64" else B
+    R32 = R0.astype(np.float32).astype(np.float64) if prec != "f64" else R0
+    ref = oracle.gemm_proj(A32, B32, C, D, r) + beta * R32
+    Gp = -(-(-(-K // L)) // KB[prec]) * KB[prec]
+    bound = _tol.gemm_bound(prec, L, r, Gp, _tol.magnitude(A32, B32, C, D, r)) + 4 * 2 ** -23 * abs(beta) * np.abs(R32)
+    if prec.startswith("fp8"):
+        bound = bound + 4.0 * _tol.fp8_floor(A32, B32, C, D, r, prec)
+    _tol.assert_within(R.double().cpu().numpy(), ref, bound, f"split {prec} r={r} L={L} K={K}")
