@@ -112,7 +112,11 @@ int pj_basis_destroy(pj_basis b);
 
 /* --------------------------------------------------------- projected GEMM */
 
-/* Bytes of workspace proj_gemm needs (0 for invalid arguments). */
+/* Bytes of workspace proj_gemm needs (0 for invalid arguments): the two
+ * packed operands, plus, when the output is too small to fill the device
+ * with tiles and the contraction is long (skinny outputs such as scatter or
+ * Gram matrices), room for the partial results of contiguous ranges of the
+ * contraction that are contracted concurrently and summed afterwards. */
 size_t pj_gemm_workspace_bytes(int M, int W, int K, int L, int r, int prec);
 
 /* R <- A Q_{r,K} B + beta R  (paper Sec. III-A/B, eq. (5)-(8), (15)).
