@@ -244,10 +244,12 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
         bok[i] = c < NCH && cb < k_nrb;
         bsrc[i] = Kp + ((bok[i] ? cb : 0) * k_nkb * 64 + lc) * 16;
     }
-    f32x4 bst[B_PER_T];
-    float ast[A_PER_T];
+    // two register sets: the loads of step st + 2 are issued while step st is
+    // contracted (two k-blocks of work to hide each global load behind)
+    f32x4 bst0[B_PER_T], bst1[B_PER_T];
+    float ast0[A_PER_T], ast1[A_PER_T];
     // step st: projection l = l_hi - 1 - st / kpl (highest first), kernel blocks c0 = 8 (st % kpl)
-    auto gload = [&](int64_t st) {
+    auto gload = [&](int64_t st, float (&ast)[A_PER_T], f32x4 (&bst)[B_PER_T]) {
         const int64_t l = l_hi - 1 - st / kpl;
         const int64_t cblk = st % kpl;
         const int64_t kb = l * kpl + cblk;
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
         for (int i = 0; i < B_PER_T; ++i)
             bst[i] = bok[i] ? *reinterpret_cast<const f32x4*>(bsrc[i] + kb * 1024) : f32x4{0.f, 0.f, 0.f, 0.f};
     };
-    auto swrite = [&](int s) {
+    auto swrite = [&](int s, const float (&ast)[A_PER_T], const f32x4 (&bst)[B_PER_T]) {
 #pragma unroll
         for (int i = 0; i < A_PER_T; ++i) {
             const int x = tid + i * NT;
@@ -285,14 +287,10 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
 #pragma unroll
             for (int j = 0; j < 16; ++j) tot[a][b][j] = acc[a][b][j] = 0.0f;
 
-    if (nst > 0) {
-        gload(0);
-        swrite(0);
-    }
-    __syncthreads();
-    for (int64_t st = 0; st < nst; ++st) {
+    auto step = [&](int64_t st, float (&la)[A_PER_T], f32x4 (&lb)[B_PER_T], const float (&sa)[A_PER_T],
+                    const f32x4 (&sb)[B_PER_T]) {
         const int s = (int)(st & 1);
-        if (st + 1 < nst) gload(st + 1);
+        if (st + 2 < nst) gload(st + 2, la, lb);
         f32x4 xf[WM], yf[WN];
 #pragma unroll
         for (int a = 0; a < WM; ++a) {
@@ -321,8 +319,18 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
                         acc[a][b][j] = 0.0f;
                     }
         }
-        if (st + 1 < nst) swrite(s ^ 1);
+        if (st + 1 < nst) swrite(s ^ 1, sa, sb);
         __syncthreads();
+    };
+    if (nst > 0) {
+        gload(0, ast0, bst0);
+        swrite(0, ast0, bst0);
+    }
+    if (nst > 1) gload(1, ast1, bst1);
+    __syncthreads();
+    for (int64_t st = 0; st < nst; st += 2) {
+        step(st, ast0, bst0, ast1, bst1);
+        if (st + 1 < nst) step(st + 1, ast1, bst1, ast0, bst0);
     }
 
     float* dst = nsplit == 1 ? y : part + (int64_t)sp * nout;
