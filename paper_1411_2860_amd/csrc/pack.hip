@@ -22,6 +22,9 @@
 // grid), so the small A side overlaps with the large B side.
 #include <vector>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "common.h"
 
 namespace pj {
@@ -121,6 +124,22 @@ template <int PREC> struct Cmap {
     static constexpr int NGc = ly.KB / Ec;
     static constexpr int TRc = 64 / NGc;
 };
+
+// The projection runs on the FP32 matrix cores (16 x 16 x 4 MFMA: 16 rows x
+// 16 projections per instruction) for FP32 input, 32-row tiles and passes of
+// exactly 16 projections; otherwise (a single projection, FP8's 8-row tiles,
+// FP64, 64-projection passes) as vector FMAs.
+template <typename TIn, int PREC, int RL, int NCH>
+constexpr bool pack_mfma()
+{
+    return std::is_same<TIn, float>::value && Cmap<PREC>::TRc == 32 && 4 * NCH * RL == 16 &&
+           (PREC == P_F32 || PREC == P_BF16 || PREC == P_BF16X3 || PREC == P_F16 || PREC == P_F16X3);
+}
+
+// LDS floats per projection of the transpose that returns the matrix-core
+// results to the lane layout of the stores: 32 rows x KB groups, padded.
+template <int PREC>
+constexpr int pack_mfma_ds() { return 32 * layout_of(PREC).KB + 4; }
 
 __device__ __forceinline__ unsigned fp8_exp_byte(float amax, float& inv, float& sc)
 {
@@ -231,6 +250,104 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
     using ConstTIn = const __attribute__((address_space(4))) TIn;
     ConstTIn* coefc = (ConstTIn*)(J.coef);
 
+    // staging of one round: t0 .. t0 + TC of every group of the tile into LDS
+    auto stage = [&](int t0) {
+        if (J.vec4 && !J.trans) {
+            // 16-byte loads along the contiguous contraction index; every
+            // load of a thread is issued before its first LDS store
+            const int n4 = TRc * KB * (TC / 4);
+            V4 buf[kMaxV4];
+#pragma unroll
+            for (int i = 0; i < kMaxV4; ++i) {
+                const int idx = threadIdx.x + i * kPackThreads;
+                buf[i] = V4{0, 0, 0, 0};
+                if (idx < n4) {
+                    const int tt4 = idx % (TC / 4);
+                    const int q = idx / (TC / 4);
+                    const int jj = q % KB, rr = q / KB;
+                    const int64_t p = p0 + rr;
+                    const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
+                    if (p < J.P && k < J.K) buf[i] = *reinterpret_cast<const V4*>(X + p * J.ld + k);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kMaxV4; ++i) {
+                const int idx = threadIdx.x + i * kPackThreads;
+                if (idx < n4) {
+                    const int tt4 = idx % (TC / 4);
+                    const int q = idx / (TC / 4);
+                    const int jj = q % KB, rr = q / KB;
+                    *reinterpret_cast<V4*>(lds + rr * RS + jj * JS + 4 * tt4) = buf[i];
+                }
+            }
+        } else if (J.vec4) {
+            // strided source: 4 rows x 4 indices per thread, 16-byte loads
+            // along the rows, transposed in registers (all loads first)
+            const int n16 = (TRc / 4) * KB * (TC / 4);
+            V4 col[kMaxV16][4];
+#pragma unroll
+            for (int s = 0; s < kMaxV16; ++s) {
+                const int idx = threadIdx.x + s * kPackThreads;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) col[s][i] = V4{0, 0, 0, 0};
+                if (idx < n16) {
+                    const int rr4 = idx % (TRc / 4);
+                    const int q = idx / (TRc / 4);
+                    const int tt4 = q % (TC / 4), jj = q / (TC / 4);
+                    const int64_t p = p0 + 4 * rr4;
+                    const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (k + i < J.K) {
+                            if (p + 3 < J.P) {
+                                col[s][i] = *reinterpret_cast<const V4*>(X + (k + i) * J.ld + p);
+                            } else {
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    if (p + u < J.P) col[s][i][u] = X[(k + i) * J.ld + p + u];
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < kMaxV16; ++s) {
+                const int idx = threadIdx.x + s * kPackThreads;
+                if (idx < n16) {
+                    const int rr4 = idx % (TRc / 4);
+                    const int q = idx / (TRc / 4);
+                    const int tt4 = q % (TC / 4), jj = q / (TC / 4);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const V4 w = {col[s][0][u], col[s][1][u], col[s][2][u], col[s][3][u]};
+                        *reinterpret_cast<V4*>(lds + (4 * rr4 + u) * RS + jj * JS + 4 * tt4) = w;
+                    }
+                }
+            }
+        } else {
+            const int n1 = TRc * KB * TCp;
+            for (int idx = threadIdx.x; idx < n1; idx += kPackThreads) {
+                int rr, jj, tt;
+                if (!J.trans) {
+                    tt = idx % TCp;
+                    const int q = idx / TCp;
+                    jj = q % KB;
+                    rr = q / KB;
+                } else {
+                    rr = idx % TRc;
+                    const int q = idx / TRc;
+                    tt = q % TCp;
+                    jj = q / TCp;
+                }
+                const int64_t p = p0 + rr;
+                const int64_t k = (j0 + jj) * L + t0 + tt;
+                TIn v = (TIn)0;
+                if (tt < TC && p < J.P && k < J.K) v = J.trans ? X[k * J.ld + p] : X[p * J.ld + k];
+                lds[rr * RS + jj * JS + tt] = v;
+            }
+        }
+    };
+
     for (int lp = 0; lp < r; lp += 4 * NCH * RL) {
         TIn acc[NCH][RL][Ec];
 #pragma unroll
@@ -240,136 +357,99 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 #pragma unroll
                 for (int e = 0; e < Ec; ++e) acc[c][q][e] = (TIn)0;
 
-        for (int t0 = 0; t0 < L; t0 += TC) {
-            __syncthreads();
-            if (J.vec4 && !J.trans) {
-                // 16-byte loads along the contiguous contraction index; every
-                // load of a thread is issued before its first LDS store
-                const int n4 = TRc * KB * (TC / 4);
-                V4 buf[kMaxV4];
+        if constexpr (pack_mfma<TIn, PREC, RL, NCH>()) {
+            // Matrix cores: wave w contracts groups w * GPW .. w * GPW + GPW - 1
+            // of the tile for the 16 projections lp .. lp + 15, two 16-row
+            // halves each; lane (i, kq) supplies data row i / coefficient
+            // column i at contraction index 4 s + kq.
+            constexpr int GPW = KB / 4;
+            constexpr int kMaxS = 16;
+            const int i16 = lane & 15, kq = lane >> 4;
+            f32x4 macc[GPW][2];
 #pragma unroll
-                for (int i = 0; i < kMaxV4; ++i) {
-                    const int idx = threadIdx.x + i * kPackThreads;
-                    buf[i] = V4{0, 0, 0, 0};
-                    if (idx < n4) {
-                        const int tt4 = idx % (TC / 4);
-                        const int q = idx / (TC / 4);
-                        const int jj = q % KB, rr = q / KB;
-                        const int64_t p = p0 + rr;
-                        const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
-                        if (p < J.P && k < J.K) buf[i] = *reinterpret_cast<const V4*>(X + p * J.ld + k);
-                    }
-                }
+            for (int gi = 0; gi < GPW; ++gi)
 #pragma unroll
-                for (int i = 0; i < kMaxV4; ++i) {
-                    const int idx = threadIdx.x + i * kPackThreads;
-                    if (idx < n4) {
-                        const int tt4 = idx % (TC / 4);
-                        const int q = idx / (TC / 4);
-                        const int jj = q % KB, rr = q / KB;
-                        *reinterpret_cast<V4*>(lds + rr * RS + jj * JS + 4 * tt4) = buf[i];
-                    }
-                }
-            } else if (J.vec4) {
-                // strided source: 4 rows x 4 indices per thread, 16-byte loads
-                // along the rows, transposed in registers (all loads first)
-                const int n16 = (TRc / 4) * KB * (TC / 4);
-                V4 col[kMaxV16][4];
+                for (int h = 0; h < 2; ++h) macc[gi][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int t0 = 0; t0 < L; t0 += TC) {
+                float cB[kMaxS];
+                const int lcol = min(lp + i16, L - 1);     // columns >= r are never stored
 #pragma unroll
-                for (int s = 0; s < kMaxV16; ++s) {
-                    const int idx = threadIdx.x + s * kPackThreads;
+                for (int si = 0; si < kMaxS; ++si)
+                    cB[si] = si < TCp / 4 ? (float)J.coef[(int64_t)min(t0 + 4 * si + kq, L - 1) * L + lcol] : 0.0f;
+                __syncthreads();
+                stage(t0);
+                __syncthreads();
+                for (int si = 0; si < TCp / 4; ++si) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) col[s][i] = V4{0, 0, 0, 0};
-                    if (idx < n16) {
-                        const int rr4 = idx % (TRc / 4);
-                        const int q = idx / (TRc / 4);
-                        const int tt4 = q % (TC / 4), jj = q / (TC / 4);
-                        const int64_t p = p0 + 4 * rr4;
-                        const int64_t k = (j0 + jj) * L + t0 + 4 * tt4;
+                    for (int gi = 0; gi < GPW; ++gi) {
+                        const int gg = wave * GPW + gi;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            if (k + i < J.K) {
-                                if (p + 3 < J.P) {
-                                    col[s][i] = *reinterpret_cast<const V4*>(X + (k + i) * J.ld + p);
-                                } else {
-#pragma unroll
-                                    for (int u = 0; u < 4; ++u)
-                                        if (p + u < J.P) col[s][i][u] = X[(k + i) * J.ld + p + u];
-                                }
-                            }
+                        for (int h = 0; h < 2; ++h) {
+                            const float av = (float)lds[(h * 16 + i16) * RS + gg * JS + 4 * si + kq];
+                            macc[gi][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cB[si], macc[gi][h], 0, 0, 0);
                         }
                     }
-                }
-#pragma unroll
-                for (int s = 0; s < kMaxV16; ++s) {
-                    const int idx = threadIdx.x + s * kPackThreads;
-                    if (idx < n16) {
-                        const int rr4 = idx % (TRc / 4);
-                        const int q = idx / (TRc / 4);
-                        const int tt4 = q % (TC / 4), jj = q / (TC / 4);
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const V4 w = {col[s][0][u], col[s][1][u], col[s][2][u], col[s][3][u]};
-                            *reinterpret_cast<V4*>(lds + (4 * rr4 + u) * RS + jj * JS + 4 * tt4) = w;
-                        }
-                    }
-                }
-            } else {
-                const int n1 = TRc * KB * TCp;
-                for (int idx = threadIdx.x; idx < n1; idx += kPackThreads) {
-                    int rr, jj, tt;
-                    if (!J.trans) {
-                        tt = idx % TCp;
-                        const int q = idx / TCp;
-                        jj = q % KB;
-                        rr = q / KB;
-                    } else {
-                        rr = idx % TRc;
-                        const int q = idx / TRc;
-                        tt = q % TCp;
-                        jj = q / TCp;
-                    }
-                    const int64_t p = p0 + rr;
-                    const int64_t k = (j0 + jj) * L + t0 + tt;
-                    TIn v = (TIn)0;
-                    if (tt < TC && p < J.P && k < J.K) v = J.trans ? X[k * J.ld + p] : X[p * J.ld + k];
-                    lds[rr * RS + jj * JS + tt] = v;
                 }
             }
+            // back to the lane layout of the stores through LDS:
+            // Dt[ll][row][group], ll = projection - lp
+            constexpr int DS = pack_mfma_ds<PREC>();
+            float* Dt = reinterpret_cast<float*>(lds);
             __syncthreads();
-            for (int tt4 = 0; tt4 < TCp / 4; ++tt4) {
-                const int tb = t0 + 4 * tt4;
-                // wave-uniform coefficients through the constant address space
-                // (scalar loads).  Indices are clamped into the L x L matrix: a
-                // clamped t only meets zero data (t >= t0 + TC is zero-padded in
-                // LDS) and a clamped projection l >= r is never stored.
-                TIn cf[NCH][4][RL];
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const int lb = lp + (wave + 4 * c) * RL;
+            for (int gi = 0; gi < GPW; ++gi)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int t = min(tb + i, L - 1);
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                        for (int q = 0; q < RL; ++q) cf[c][i][q] = coefc[(int64_t)t * L + min(lb + q, L - 1)];
-                    }
+                    for (int j = 0; j < 4; ++j)
+                        Dt[i16 * DS + (h * 16 + 4 * kq + j) * KB + wave * GPW + gi] = macc[gi][h][j];
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    const int ll = (wave + 4 * c) * RL + q;
+#pragma unroll
+                    for (int e = 0; e < Ec; ++e) acc[c][q][e] = (TIn)Dt[ll * DS + row * KB + g * Ec + e];
                 }
+        } else {
+            for (int t0 = 0; t0 < L; t0 += TC) {
+                __syncthreads();
+                stage(t0);
+                __syncthreads();
+                for (int tt4 = 0; tt4 < TCp / 4; ++tt4) {
+                    const int tb = t0 + 4 * tt4;
+                    // wave-uniform coefficients through the constant address space
+                    // (scalar loads).  Indices are clamped into the L x L matrix: a
+                    // clamped t only meets zero data (t >= t0 + TC is zero-padded in
+                    // LDS) and a clamped projection l >= r is never stored.
+                    TIn cf[NCH][4][RL];
 #pragma unroll
-                for (int e = 0; e < Ec; ++e) {
-                    const V4 v = *reinterpret_cast<const V4*>(lds + row * RS + (g * Ec + e) * JS + 4 * tt4);
+                    for (int c = 0; c < NCH; ++c) {
+                        const int lb = lp + (wave + 4 * c) * RL;
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c)
+                        for (int i = 0; i < 4; ++i) {
+                            const int t = min(tb + i, L - 1);
 #pragma unroll
-                        for (int q = 0; q < RL; ++q) {
-                            acc[c][q][e] += v[0] * cf[c][0][q];
-                            acc[c][q][e] += v[1] * cf[c][1][q];
-                            acc[c][q][e] += v[2] * cf[c][2][q];
-                            acc[c][q][e] += v[3] * cf[c][3][q];
+                            for (int q = 0; q < RL; ++q) cf[c][i][q] = coefc[(int64_t)t * L + min(lb + q, L - 1)];
                         }
+                    }
+#pragma unroll
+                    for (int e = 0; e < Ec; ++e) {
+                        const V4 v = *reinterpret_cast<const V4*>(lds + row * RS + (g * Ec + e) * JS + 4 * tt4);
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                            for (int q = 0; q < RL; ++q) {
+                                acc[c][q][e] += v[0] * cf[c][0][q];
+                                acc[c][q][e] += v[1] * cf[c][1][q];
+                                acc[c][q][e] += v[2] * cf[c][2][q];
+                                acc[c][q][e] += v[3] * cf[c][3][q];
+                            }
+                    }
                 }
             }
         }
-
         const int rib = rib0 + row;   // row within the packed row block
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -479,7 +559,9 @@ int launch_t(const PackArgs* a, int n, hipStream_t s)
     const int64_t na = ja.nrt * ja.ngt;
     const int64_t nb = n > 1 ? jb.nrt * jb.ngt : 0;
     const int rs = ja.RS > jb.RS ? ja.RS : jb.RS;
-    const size_t lds = (size_t)Cmap<PREC>::TRc * rs * sizeof(TIn);
+    size_t lds = (size_t)Cmap<PREC>::TRc * rs * sizeof(TIn);
+    if constexpr (pack_mfma<TIn, PREC, RL, NCH>())
+        lds = std::max(lds, (size_t)16 * pack_mfma_ds<PREC>() * sizeof(float));
     (void)ly;
     if (na + nb > 0x7fffffff) return -2;
     hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH>), dim3((unsigned)(na + nb)), dim3(kPackThreads), lds, s,
@@ -521,7 +603,9 @@ int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
     if (hipMemcpyAsync(t + rup(jb, 256), prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return -1;
-    const size_t lds = (size_t)Cmap<PREC>::TRc * rs * sizeof(TIn);
+    size_t lds = (size_t)Cmap<PREC>::TRc * rs * sizeof(TIn);
+    if constexpr (pack_mfma<TIn, PREC, RL, NCH>())
+        lds = std::max(lds, (size_t)16 * pack_mfma_ds<PREC>() * sizeof(float));
     (void)ly;
     hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH>), dim3((unsigned)prefix[n]), dim3(kPackThreads),
                        lds, s, (const PackJob<TIn>*)t, (const int64_t*)(t + rup(jb, 256)), n);
