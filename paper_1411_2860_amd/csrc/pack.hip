@@ -48,6 +48,11 @@ struct PackJob {
     int64_t nrb, ngt;   // row blocks, group tiles (Gp / KB)
     int64_t nrt;        // row tiles of the compute mapping
     int TC, TCp, JS, RS;
+    // Swizzled round layout (FP32 input, TC / 4 a power of two): row rr of
+    // the tile holds NC = KB * TC / 4 chunks of 4 values without padding,
+    // chunk c = group * TC / 4 + t / 4 at slot c ^ (rr & SM), so that the
+    // 16 rows read by one matrix-core step fall in distinct banks.
+    int swz, lnc, ltc4, sm;
 };
 
 // ---- OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits,
@@ -106,6 +111,13 @@ __device__ __forceinline__ void store_lane(char* __restrict__ out, int64_t off, 
         *reinterpret_cast<f16x8*>(out + off) = hi;
         if constexpr (PREC == P_F16X3) *reinterpret_cast<f16x8*>(out + plane_stride + off) = lo;
     }
+}
+
+// 16 bytes per lane from global memory straight into LDS: lane i writes
+// dst + 4 i (dst is the same for the whole wave).
+__device__ __forceinline__ void lds_direct16(const float* src, float* dst)
+{
+    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
 }
 
 template <typename TIn> struct Vec4;
@@ -223,7 +235,7 @@ __device__ __forceinline__ void store_fp8_quarter(char* __restrict__ out, int64_
     }
 }
 
-template <typename TIn, int PREC, int RL, int NCH>
+template <typename TIn, int PREC, int RL, int NCH, bool DMA>
 __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 {
     constexpr Layout ly = layout_of(PREC);
@@ -250,8 +262,47 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
     using ConstTIn = const __attribute__((address_space(4))) TIn;
     ConstTIn* coefc = (ConstTIn*)(J.coef);
 
+    // LDS element index of (row rr, group jj, index t of the round): the
+    // swizzled layout with direct loads, else rows of RS with padding
+    const int lnc = J.lnc, ltc4 = J.ltc4, sm = J.sm;
+    auto loff = [&](int rr, int jj, int t) -> int {
+        if constexpr (DMA) return ((rr << lnc) + (((jj << ltc4) + (t >> 2)) ^ (rr & sm))) * 4 + (t & 3);
+        else return rr * RS + jj * JS + t;
+    };
+
     // staging of one round: t0 .. t0 + TC of every group of the tile into LDS
     auto stage = [&](int t0) {
+        if constexpr (DMA) {
+            // swizzled layout filled by direct loads: the 16-byte chunks go
+            // from memory straight into LDS (no registers), each wave
+            // instruction filling 64 consecutive slots.  Chunks outside the
+            // operand (rows >= P, indices >= K; K is a multiple of 4 here)
+            // are read from X itself and then overwritten with zeros.
+            const int per_wave = (TRc << lnc) / kPackThreads;
+            const bool interior = p0 + TRc <= J.P && (j0 + KB - 1) * L + t0 + TC <= J.K;
+            const TIn* __restrict__ base = X + p0 * J.ld + j0 * L + t0;
+            unsigned outside = 0;
+            for (int i = 0; i < per_wave; ++i) {
+                const int slot0 = (wave * per_wave + i) * 64;
+                const int gsl = slot0 + lane;
+                const int rr = gsl >> lnc;
+                const int c = (gsl & ((1 << lnc) - 1)) ^ (rr & sm);
+                const int64_t ko = (c >> ltc4) * L + 4 * (c & ((1 << ltc4) - 1));
+                const TIn* src = base + rr * J.ld + ko;
+                if (!interior && (p0 + rr >= J.P || j0 * L + t0 + ko >= J.K)) {
+                    src = X;
+                    outside |= 1u << i;
+                }
+                lds_direct16(src, lds + slot0 * 4);
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (!interior) {
+                for (int i = 0; i < per_wave; ++i)
+                    if (outside & (1u << i))
+                        *reinterpret_cast<V4*>(lds + ((wave * per_wave + i) * 64 + lane) * 4) = V4{0, 0, 0, 0};
+            }
+            return;
+        }
         if (J.vec4 && !J.trans) {
             // 16-byte loads along the contiguous contraction index; every
             // load of a thread is issued before its first LDS store
@@ -277,7 +328,7 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                     const int tt4 = idx % (TC / 4);
                     const int q = idx / (TC / 4);
                     const int jj = q % KB, rr = q / KB;
-                    *reinterpret_cast<V4*>(lds + rr * RS + jj * JS + 4 * tt4) = buf[i];
+                    *reinterpret_cast<V4*>(lds + loff(rr, jj, 4 * tt4)) = buf[i];
                 }
             }
         } else if (J.vec4) {
@@ -320,7 +371,7 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const V4 w = {col[s][0][u], col[s][1][u], col[s][2][u], col[s][3][u]};
-                        *reinterpret_cast<V4*>(lds + (4 * rr4 + u) * RS + jj * JS + 4 * tt4) = w;
+                        *reinterpret_cast<V4*>(lds + loff(4 * rr4 + u, jj, 4 * tt4)) = w;
                     }
                 }
             }
@@ -343,7 +394,7 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                 const int64_t k = (j0 + jj) * L + t0 + tt;
                 TIn v = (TIn)0;
                 if (tt < TC && p < J.P && k < J.K) v = J.trans ? X[k * J.ld + p] : X[p * J.ld + k];
-                lds[rr * RS + jj * JS + tt] = v;
+                lds[loff(rr, jj, tt)] = v;
             }
         }
     };
@@ -379,15 +430,44 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                 __syncthreads();
                 stage(t0);
                 __syncthreads();
-                for (int si = 0; si < TCp / 4; ++si) {
+                // steps fully unrolled (static coefficient registers); the LDS
+                // reads of step s + 1 are issued before the products of step s
+                const int nS = TCp / 4;
+                // element (row h * 16 + i16, group gi of the wave, index
+                // 4 s + kq) at ab[gi][h] + (ax[gi] ^ 4 s): the swizzle
+                // flips chunk bits, the padded layout has ax = 0
+                const TIn* ab[GPW][2];
+                int ax[GPW];
 #pragma unroll
-                    for (int gi = 0; gi < GPW; ++gi) {
-                        const int gg = wave * GPW + gi;
+                for (int gi = 0; gi < GPW; ++gi) {
+                    const int jj = wave * GPW + gi;
+                    ax[gi] = DMA ? (((jj << ltc4) ^ (i16 & sm)) << 2) : 0;
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const float av = (float)lds[(h * 16 + i16) * RS + gg * JS + 4 * si + kq];
-                            macc[gi][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cB[si], macc[gi][h], 0, 0, 0);
+                    for (int h = 0; h < 2; ++h)
+                        ab[gi][h] = DMA ? lds + (((h * 16 + i16) << lnc) << 2) + kq
+                                        : lds + (h * 16 + i16) * RS + jj * JS + kq;
+                }
+                float av[2][GPW][2];
+#pragma unroll
+                for (int gi = 0; gi < GPW; ++gi)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) av[0][gi][h] = (float)ab[gi][h][ax[gi]];
+#pragma unroll
+                for (int si = 0; si < kMaxS; ++si) {
+                    if (si < nS) {
+                        if (si + 1 < nS) {
+#pragma unroll
+                            for (int gi = 0; gi < GPW; ++gi)
+#pragma unroll
+                                for (int h = 0; h < 2; ++h)
+                                    av[(si + 1) & 1][gi][h] = (float)ab[gi][h][ax[gi] ^ (4 * (si + 1))];
                         }
+#pragma unroll
+                        for (int gi = 0; gi < GPW; ++gi)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h)
+                                macc[gi][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[si & 1][gi][h], cB[si],
+                                                                                   macc[gi][h], 0, 0, 0);
                     }
                 }
             }
@@ -436,7 +516,7 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                     }
 #pragma unroll
                     for (int e = 0; e < Ec; ++e) {
-                        const V4 v = *reinterpret_cast<const V4*>(lds + row * RS + (g * Ec + e) * JS + 4 * tt4);
+                        const V4 v = *reinterpret_cast<const V4*>(lds + loff(row, g * Ec + e, 4 * tt4));
 #pragma unroll
                         for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -484,17 +564,28 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 }
 
 // Two jobs passed by value (one GEMM's A and B sides).
-template <typename TIn, int PREC, int RL, int NCH>
-__global__ __launch_bounds__(kPackThreads) void pack_kernel(PackJob<TIn> ja, PackJob<TIn> jb, int64_t nblk_a)
+// Waves per SIMD the register allocation must allow: 4 for the FP32
+// matrix-core variant with direct loads (its 32 KB rounds fit 4 workgroups
+// per CU), else the compiler's choice.
+template <typename TIn, int PREC, int RL, int NCH, bool DMA>
+constexpr int pack_waves_per_eu()
 {
-    if ((int64_t)blockIdx.x < nblk_a) pack_tile<TIn, PREC, RL, NCH>(ja, (int64_t)blockIdx.x);
-    else pack_tile<TIn, PREC, RL, NCH>(jb, (int64_t)blockIdx.x - nblk_a);
+    return DMA && PREC == P_F32 && pack_mfma<TIn, PREC, RL, NCH>() ? 4 : 1;
+}
+
+template <typename TIn, int PREC, int RL, int NCH, bool DMA>
+__global__ __launch_bounds__(kPackThreads)
+__attribute__((amdgpu_waves_per_eu(pack_waves_per_eu<TIn, PREC, RL, NCH, DMA>()))) void pack_kernel(PackJob<TIn> ja, PackJob<TIn> jb, int64_t nblk_a)
+{
+    if ((int64_t)blockIdx.x < nblk_a) pack_tile<TIn, PREC, RL, NCH, DMA>(ja, (int64_t)blockIdx.x);
+    else pack_tile<TIn, PREC, RL, NCH, DMA>(jb, (int64_t)blockIdx.x - nblk_a);
 }
 
 // Any number of jobs from a device table; prefix[i] is the first workgroup
 // of job i (prefix[njobs] = grid size).
-template <typename TIn, int PREC, int RL, int NCH>
-__global__ __launch_bounds__(kPackThreads) void pack_grouped_kernel(const PackJob<TIn>* __restrict__ jobs,
+template <typename TIn, int PREC, int RL, int NCH, bool DMA>
+__global__ __launch_bounds__(kPackThreads)
+__attribute__((amdgpu_waves_per_eu(pack_waves_per_eu<TIn, PREC, RL, NCH, DMA>()))) void pack_grouped_kernel(const PackJob<TIn>* __restrict__ jobs,
                                                                     const int64_t* __restrict__ prefix, int njobs)
 {
     const int64_t b = blockIdx.x;
@@ -504,7 +595,7 @@ __global__ __launch_bounds__(kPackThreads) void pack_grouped_kernel(const PackJo
         if (prefix[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    pack_tile<TIn, PREC, RL, NCH>(jobs[lo], b - prefix[lo]);
+    pack_tile<TIn, PREC, RL, NCH, DMA>(jobs[lo], b - prefix[lo]);
 }
 
 template <typename TIn, int PREC>
@@ -547,7 +638,27 @@ PackJob<TIn> make_job(const PackArgs& a)
     j.TCp = (TC + 3) / 4 * 4;
     j.JS = j.TCp + 4;
     j.RS = ly.KB * j.JS + 4;
+    // direct loads into the swizzled layout: FP32 rows contiguous along k,
+    // TC / 4 a power of two, the tile's chunks filling whole 64-slot wave
+    // instructions (at most 32 per wave)
+    const int tc4 = TC / 4;
+    const int nc = ly.KB * tc4;
+    j.swz = std::is_same<TIn, float>::value && j.vec4 && !j.trans && tc4 > 0 && (tc4 & (tc4 - 1)) == 0 &&
+            (Cmap<PREC>::TRc * nc) % kPackThreads == 0 && Cmap<PREC>::TRc * nc <= 32 * kPackThreads;
+    j.lnc = j.ltc4 = j.sm = 0;
+    if (j.swz) {
+        while ((1 << j.lnc) < nc) ++j.lnc;
+        while ((1 << j.ltc4) < tc4) ++j.ltc4;
+        j.sm = (nc < 16 ? nc : 16) - 1;
+    }
     return j;
+}
+
+// LDS floats (or doubles) of one staged round.
+template <typename TIn, int PREC>
+size_t round_lds_elems(const PackJob<TIn>& j, bool dma)
+{
+    return (size_t)Cmap<PREC>::TRc * (dma ? ((size_t)4 << j.lnc) : (size_t)j.RS);
 }
 
 template <typename TIn, int PREC, int RL, int NCH>
@@ -558,13 +669,20 @@ int launch_t(const PackArgs* a, int n, hipStream_t s)
     PackJob<TIn> jb = n > 1 ? make_job<TIn, PREC>(a[1]) : ja;
     const int64_t na = ja.nrt * ja.ngt;
     const int64_t nb = n > 1 ? jb.nrt * jb.ngt : 0;
-    const int rs = ja.RS > jb.RS ? ja.RS : jb.RS;
-    size_t lds = (size_t)Cmap<PREC>::TRc * rs * sizeof(TIn);
+    const bool dma = ja.swz && jb.swz;
+    size_t lds = std::max(round_lds_elems<TIn, PREC>(ja, dma), round_lds_elems<TIn, PREC>(jb, dma)) * sizeof(TIn);
     if constexpr (pack_mfma<TIn, PREC, RL, NCH>())
         lds = std::max(lds, (size_t)16 * pack_mfma_ds<PREC>() * sizeof(float));
     (void)ly;
     if (na + nb > 0x7fffffff) return -2;
-    hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH>), dim3((unsigned)(na + nb)), dim3(kPackThreads), lds, s,
+    if constexpr (std::is_same<TIn, float>::value) {
+        if (dma) {
+            hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH, true>), dim3((unsigned)(na + nb)), dim3(kPackThreads),
+                               lds, s, ja, jb, na);
+            return hipGetLastError() == hipSuccess ? 0 : -1;
+        }
+    }
+    hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH, false>), dim3((unsigned)(na + nb)), dim3(kPackThreads), lds, s,
                        ja, jb, na);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -590,12 +708,14 @@ int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
     constexpr Layout ly = layout_of(PREC);
     std::vector<PackJob<TIn>> jobs(n);
     std::vector<int64_t> prefix(n + 1, 0);
-    int rs = 0;
+    bool dma = true;
     for (int i = 0; i < n; ++i) {
         jobs[i] = make_job<TIn, PREC>(a[i]);
         prefix[i + 1] = prefix[i] + jobs[i].nrt * jobs[i].ngt;
-        rs = jobs[i].RS > rs ? jobs[i].RS : rs;
+        dma = dma && jobs[i].swz;
     }
+    size_t lds_e = 0;
+    for (int i = 0; i < n; ++i) lds_e = std::max(lds_e, round_lds_elems<TIn, PREC>(jobs[i], dma));
     if (prefix[n] > 0x7fffffff || prefix[n] == 0) return -2;
     char* t = (char*)table;
     const size_t jb = sizeof(PackJob<TIn>) * n;
@@ -603,12 +723,20 @@ int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
     if (hipMemcpyAsync(t + rup(jb, 256), prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return -1;
-    size_t lds = (size_t)Cmap<PREC>::TRc * rs * sizeof(TIn);
+    size_t lds = lds_e * sizeof(TIn);
     if constexpr (pack_mfma<TIn, PREC, RL, NCH>())
         lds = std::max(lds, (size_t)16 * pack_mfma_ds<PREC>() * sizeof(float));
     (void)ly;
-    hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH>), dim3((unsigned)prefix[n]), dim3(kPackThreads),
-                       lds, s, (const PackJob<TIn>*)t, (const int64_t*)(t + rup(jb, 256)), n);
+    if constexpr (std::is_same<TIn, float>::value) {
+        if (dma) {
+            hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, true>), dim3((unsigned)prefix[n]),
+                               dim3(kPackThreads), lds, s, (const PackJob<TIn>*)t, (const int64_t*)(t + rup(jb, 256)),
+                               n);
+            return hipGetLastError() == hipSuccess ? 0 : -1;
+        }
+    }
+    hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, false>), dim3((unsigned)prefix[n]),
+                       dim3(kPackThreads), lds, s, (const PackJob<TIn>*)t, (const int64_t*)(t + rup(jb, 256)), n);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
