@@ -139,8 +139,8 @@ template <int PREC> struct Cmap {
 
 // The projection runs on the FP32 matrix cores (16 x 16 x 4 MFMA: 16 rows x
 // 16 projections per instruction) for FP32 input, 32-row tiles and passes of
-// exactly 16 projections; otherwise (a single projection, FP8's 8-row tiles,
-// FP64, 64-projection passes) as vector FMAs.
+// 16 projections (as many passes as r needs); otherwise (a single
+// projection, FP8's 8-row tiles, FP64) as vector FMAs.
 template <typename TIn, int PREC, int RL, int NCH>
 constexpr bool pack_mfma()
 {
@@ -412,62 +412,70 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
             // Matrix cores: wave w contracts groups w * GPW .. w * GPW + GPW - 1
             // of the tile for the 16 projections lp .. lp + 15, two 16-row
             // halves each; lane (i, kq) supplies data row i / coefficient
-            // column i at contraction index 4 s + kq.
+            // column i.  The contraction runs over quads of 4 chunks: in
+            // quad q lane kq reads its chunk 4 q + kq (4 indices, one 16-byte
+            // LDS read) and feeds its 4 values to 4 consecutive products, so
+            // step 4 q + e pairs lane kq with index 4 (4 q + kq) + e.
             constexpr int GPW = KB / 4;
-            constexpr int kMaxS = 16;
+            constexpr int kMaxQ = 4;           // TCp / 4 <= 16 chunks per group
             const int i16 = lane & 15, kq = lane >> 4;
+            const int tc4 = TCp / 4, nq = (tc4 + 3) / 4;
             f32x4 macc[GPW][2];
 #pragma unroll
             for (int gi = 0; gi < GPW; ++gi)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) macc[gi][h] = f32x4{0.f, 0.f, 0.f, 0.f};
-            for (int t0 = 0; t0 < L; t0 += TC) {
-                float cB[kMaxS];
-                const int lcol = min(lp + i16, L - 1);     // columns >= r are never stored
+            // chunk 4 q + kq of group gi, row half h: ab[gi][h] + 4 (ay[gi] ^ 4 q);
+            // the swizzle flips chunk bits, the padded layout has ay = kq
+            const TIn* ab[GPW][2];
+            int ay[GPW];
 #pragma unroll
-                for (int si = 0; si < kMaxS; ++si)
-                    cB[si] = si < TCp / 4 ? (float)J.coef[(int64_t)min(t0 + 4 * si + kq, L - 1) * L + lcol] : 0.0f;
+            for (int gi = 0; gi < GPW; ++gi) {
+                const int jj = wave * GPW + gi;
+                ay[gi] = DMA ? (((jj << ltc4) ^ (i16 & sm)) ^ kq) : kq;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    ab[gi][h] = DMA ? lds + (((h * 16 + i16) << lnc) << 2) : lds + (h * 16 + i16) * RS + jj * JS;
+            }
+            const int lcol = min(lp + i16, L - 1);     // columns >= r are never stored
+            for (int t0 = 0; t0 < L; t0 += TC) {
+                float cB[4 * kMaxQ];
+#pragma unroll
+                for (int q = 0; q < kMaxQ; ++q)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ch = 4 * q + kq;
+                        cB[4 * q + e] = q < nq && ch < tc4
+                                            ? (float)J.coef[(int64_t)min(t0 + 4 * ch + e, L - 1) * L + lcol] : 0.0f;
+                    }
                 __syncthreads();
                 stage(t0);
                 __syncthreads();
-                // steps fully unrolled (static coefficient registers); the LDS
-                // reads of step s + 1 are issued before the products of step s
-                const int nS = TCp / 4;
-                // element (row h * 16 + i16, group gi of the wave, index
-                // 4 s + kq) at ab[gi][h] + (ax[gi] ^ 4 s): the swizzle
-                // flips chunk bits, the padded layout has ax = 0
-                const TIn* ab[GPW][2];
-                int ax[GPW];
+                // quads fully unrolled; the reads of quad q + 1 are issued
+                // before the products of quad q
+                f32x4 av[2][GPW][2];
+                auto rdq = [&](int q, f32x4 (&d)[GPW][2]) {
+                    const bool ok = 4 * q + kq < tc4;
 #pragma unroll
-                for (int gi = 0; gi < GPW; ++gi) {
-                    const int jj = wave * GPW + gi;
-                    ax[gi] = DMA ? (((jj << ltc4) ^ (i16 & sm)) << 2) : 0;
+                    for (int gi = 0; gi < GPW; ++gi)
 #pragma unroll
-                    for (int h = 0; h < 2; ++h)
-                        ab[gi][h] = DMA ? lds + (((h * 16 + i16) << lnc) << 2) + kq
-                                        : lds + (h * 16 + i16) * RS + jj * JS + kq;
-                }
-                float av[2][GPW][2];
+                        for (int h = 0; h < 2; ++h)
+                            d[gi][h] = ok ? *reinterpret_cast<const f32x4*>(ab[gi][h] + 4 * (ay[gi] ^ (4 * q)))
+                                          : f32x4{0.f, 0.f, 0.f, 0.f};
+                };
+                rdq(0, av[0]);
 #pragma unroll
-                for (int gi = 0; gi < GPW; ++gi)
+                for (int q = 0; q < kMaxQ; ++q) {
+                    if (q < nq) {
+                        if (q + 1 < nq) rdq(q + 1, av[(q + 1) & 1]);
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) av[0][gi][h] = (float)ab[gi][h][ax[gi]];
-#pragma unroll
-                for (int si = 0; si < kMaxS; ++si) {
-                    if (si < nS) {
-                        if (si + 1 < nS) {
+                        for (int e = 0; e < 4; ++e)
 #pragma unroll
                             for (int gi = 0; gi < GPW; ++gi)
 #pragma unroll
                                 for (int h = 0; h < 2; ++h)
-                                    av[(si + 1) & 1][gi][h] = (float)ab[gi][h][ax[gi] ^ (4 * (si + 1))];
-                        }
-#pragma unroll
-                        for (int gi = 0; gi < GPW; ++gi)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h)
-                                macc[gi][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[si & 1][gi][h], cB[si],
-                                                                                   macc[gi][h], 0, 0, 0);
+                                    macc[gi][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                        av[q & 1][gi][h][e], cB[4 * q + e], macc[gi][h], 0, 0, 0);
                     }
                 }
             }
@@ -564,13 +572,15 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 }
 
 // Two jobs passed by value (one GEMM's A and B sides).
-// Waves per SIMD the register allocation must allow: 4 for the FP32
-// matrix-core variant with direct loads (its 32 KB rounds fit 4 workgroups
-// per CU), else the compiler's choice.
+// Waves per SIMD the register allocation must allow for the matrix-core
+// variants with direct loads (32 KB rounds, so LDS admits 5 workgroups per
+// CU): 4 for FP32 output, 3 for the 16-bit outputs, whose conversions need
+// more registers; else the compiler's choice.
 template <typename TIn, int PREC, int RL, int NCH, bool DMA>
 constexpr int pack_waves_per_eu()
 {
-    return DMA && PREC == P_F32 && pack_mfma<TIn, PREC, RL, NCH>() ? 4 : 1;
+    if constexpr (DMA && pack_mfma<TIn, PREC, RL, NCH>()) return PREC == P_F32 ? 4 : 3;
+    return 1;
 }
 
 template <typename TIn, int PREC, int RL, int NCH, bool DMA>
@@ -696,7 +706,9 @@ int launch_p(const PackArgs* a, int n, hipStream_t s)
     if constexpr (layout_of(PREC).E > 8) {
         return launch_t<TIn, PREC, 2, 1>(a, n, s);       // FP8: r <= 8
     } else {
-        if (r <= 16) return launch_t<TIn, PREC, 4, 1>(a, n, s);
+        // 16-projection passes on the matrix cores where they apply (every r,
+        // so that a pack at any r sums in the same order), else 64 per pass
+        if (r <= 16 || pack_mfma<TIn, PREC, 4, 1>()) return launch_t<TIn, PREC, 4, 1>(a, n, s);
         return launch_t<TIn, PREC, 4, 4>(a, n, s);
     }
 }
@@ -749,7 +761,7 @@ int launch_grouped_p(const PackArgs* a, int n, void* table, hipStream_t s)
     if constexpr (layout_of(PREC).E > 8) {
         return launch_grouped_t<TIn, PREC, 2, 1>(a, n, table, s);
     } else {
-        if (r <= 16) return launch_grouped_t<TIn, PREC, 4, 1>(a, n, table, s);
+        if (r <= 16 || pack_mfma<TIn, PREC, 4, 1>()) return launch_grouped_t<TIn, PREC, 4, 1>(a, n, table, s);
         return launch_grouped_t<TIn, PREC, 4, 4>(a, n, table, s);
     }
 }
