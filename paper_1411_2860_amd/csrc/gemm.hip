@@ -273,11 +273,19 @@ __device__ __forceinline__ void gemm_tile(
             }
 }
 
-// The same workgroup tile with the operands staged through LDS: per k-block
-// the workgroup copies its BMB + BNB packed tiles (already in fragment order,
-// 1 KiB per plane, so the copy is a plain coalesced 16-byte-per-lane stream)
-// into one of two LDS stages while its waves run the matrix instructions on
-// fragments of the other stage.  Each tile is fetched from L2 once per
+// k-blocks staged per step of the LDS-staged tile: two where both stages
+// stay within 48 KiB, which halves the barriers per contraction.
+template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+constexpr int gemm_lds_ks()
+{
+    return 2 * 2 * (WM * WAVES_M + WN * WAVES_N) * MT<PREC>::PLANES <= 48 ? 2 : 1;
+}
+
+// The same workgroup tile with the operands staged through LDS: per step of
+// KS k-blocks the workgroup copies its BMB + BNB packed tiles per k-block
+// (already in fragment order, 1 KiB per plane, so the copy is a plain
+// coalesced 16-byte-per-lane stream) into one of two LDS stages while its
+// waves run the matrix instructions on fragments of the other stage.  Each tile is fetched from L2 once per
 // workgroup instead of once per wave, and the global loads of k-block k+1
 // overlap the MFMAs of k-block k.  16-byte lane formats only (not FP8).
 template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
@@ -294,7 +302,9 @@ __device__ __forceinline__ void gemm_tile_lds(
     constexpr int NT = 64 * WAVES_M * WAVES_N;
     constexpr int BMB = WM * WAVES_M, BNB = WN * WAVES_N;
     constexpr int NTILE = (BMB + BNB) * PL;        // 1 KiB tiles per k-block
-    constexpr int NCH = NTILE * 64;                // 16-byte chunks per k-block
+    constexpr int KS = gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>();   // k-blocks per step
+    constexpr int NCH1 = NTILE * 64;               // 16-byte chunks per k-block
+    constexpr int NCH = NCH1 * KS;                 // and per step
     constexpr int PER_T = (NCH + NT - 1) / NT;
     static_assert(sizeof(frag) == 16, "LDS path is for 16-byte lane formats");
     (void)x_pb;
@@ -308,13 +318,16 @@ __device__ __forceinline__ void gemm_tile_lds(
     const int wm = wave % WAVES_M, wn = wave / WAVES_M;
     const int64_t rbB = tm * BMB, cbB = tn * BNB;
 
-    // source of chunk c of a k-block: tile ti = c / 64 = blk * PL + pl
+    // source of chunk c of a step: k-block kk[i] = c / NCH1 of the step,
+    // tile ti = (c % NCH1) / 64 = blk * PL + pl
     const char* src[PER_T];
     bool ok[PER_T];
+    int kk[PER_T];
 #pragma unroll
     for (int i = 0; i < PER_T; ++i) {
         const int c = tid + i * NT;
-        const int ti = c / 64, lc = c % 64;
+        kk[i] = c / NCH1;
+        const int ti = (c % NCH1) / 64, lc = c % 64;
         const int blk = ti / PL, pl = ti % PL;
         ok[i] = false;
         src[i] = X;
@@ -333,10 +346,14 @@ __device__ __forceinline__ void gemm_tile_lds(
     // two register sets: the loads of step st + 2 are issued while step st is
     // contracted, so each global load has two k-blocks of work to hide behind
     f32x4 stage0[PER_T], stage1[PER_T];
-    auto gload = [&](int64_t kb, f32x4 (&stage)[PER_T]) {
+    // loads of step st: k-blocks nkb - 1 - st KS - kk (zeros below k-block 0)
+    auto gload = [&](int64_t st, f32x4 (&stage)[PER_T]) {
 #pragma unroll
-        for (int i = 0; i < PER_T; ++i)
-            stage[i] = ok[i] ? *reinterpret_cast<const f32x4*>(src[i] + kb * 1024) : f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < PER_T; ++i) {
+            const int64_t kb = nkb - 1 - st * KS - kk[i];
+            stage[i] = ok[i] && kb >= 0 ? *reinterpret_cast<const f32x4*>(src[i] + kb * 1024)
+                                        : f32x4{0.f, 0.f, 0.f, 0.f};
+        }
     };
     auto swrite = [&](int s, const f32x4 (&stage)[PER_T]) {
 #pragma unroll
@@ -354,42 +371,49 @@ __device__ __forceinline__ void gemm_tile_lds(
 #pragma unroll
             for (int j = 0; j < T::NACC; ++j) acc[a][b][j] = 0;
 
-    // highest projection first (see gemm_tile): step st contracts k-block nkb - 1 - st
+    // highest projection first (see gemm_tile): step st contracts k-blocks
+    // nkb - 1 - st KS down to nkb - st KS - KS (a zero block past the end
+    // adds exact zeros)
     auto contract = [&](int s) {
-        frag fa[WM][PL], fb[WN][PL];
 #pragma unroll
-        for (int a = 0; a < WM; ++a)
+        for (int k = 0; k < KS; ++k) {
+            frag fa[WM][PL], fb[WN][PL];
+            const f32x4* base = lds + s * NCH + k * NCH1;
 #pragma unroll
-            for (int pl = 0; pl < PL; ++pl)
-                fa[a][pl] = *reinterpret_cast<const frag*>(&lds[s * NCH + ((wm * WM + a) * PL + pl) * 64 + lane]);
+            for (int a = 0; a < WM; ++a)
 #pragma unroll
-        for (int b = 0; b < WN; ++b)
+                for (int pl = 0; pl < PL; ++pl)
+                    fa[a][pl] = *reinterpret_cast<const frag*>(&base[((wm * WM + a) * PL + pl) * 64 + lane]);
 #pragma unroll
-            for (int pl = 0; pl < PL; ++pl)
-                fb[b][pl] = *reinterpret_cast<const frag*>(&lds[s * NCH + ((BMB + wn * WN + b) * PL + pl) * 64 + lane]);
+            for (int b = 0; b < WN; ++b)
 #pragma unroll
-        for (int a = 0; a < WM; ++a)
+                for (int pl = 0; pl < PL; ++pl)
+                    fb[b][pl] = *reinterpret_cast<const frag*>(&base[((BMB + wn * WN + b) * PL + pl) * 64 + lane]);
 #pragma unroll
-            for (int b = 0; b < WN; ++b) T::mma(acc[a][b], fa[a], fb[b]);
+            for (int a = 0; a < WM; ++a)
+#pragma unroll
+                for (int b = 0; b < WN; ++b) T::mma(acc[a][b], fa[a], fb[b]);
+        }
     };
     // step st (LDS buffer st & 1): issue the loads of step st + 2 into the
     // register set that held step st, contract, then park step st + 1 (the
     // other register set) in the other LDS buffer
+    const int64_t nst = (nkb + KS - 1) / KS;
     auto step = [&](int64_t st, f32x4 (&ld_set)[PER_T], const f32x4 (&st_set)[PER_T]) {
-        if (st + 2 < nkb) gload(nkb - 3 - st, ld_set);
+        if (st + 2 < nst) gload(st + 2, ld_set);
         contract((int)(st & 1));
-        if (st + 1 < nkb) swrite((int)((st + 1) & 1), st_set);
+        if (st + 1 < nst) swrite((int)((st + 1) & 1), st_set);
         __syncthreads();
     };
-    if (nkb > 0) {
-        gload(nkb - 1, stage0);
+    if (nst > 0) {
+        gload(0, stage0);
         swrite(0, stage0);
     }
-    if (nkb > 1) gload(nkb - 2, stage1);
+    if (nst > 1) gload(1, stage1);
     __syncthreads();
-    for (int64_t st = 0; st < nkb; st += 2) {
+    for (int64_t st = 0; st < nst; st += 2) {
         step(st, stage0, stage1);
-        if (st + 1 < nkb) step(st + 1, stage1, stage0);
+        if (st + 1 < nst) step(st + 1, stage1, stage0);
     }
 
     const int64_t rb0 = rbB + wm * WM, cb0 = cbB + wn * WN;
@@ -431,7 +455,8 @@ template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 constexpr size_t gemm_lds_bytes()
 {
     if constexpr (KIND == 1 && sizeof(typename MT<PREC>::frag) == 16)
-        return 2ull * (WM * WAVES_M + WN * WAVES_N) * MT<PREC>::PLANES * 1024;
+        return 2ull * gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>() * (WM * WAVES_M + WN * WAVES_N) *
+               MT<PREC>::PLANES * 1024;
     return 0;
 }
 
