@@ -276,16 +276,16 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
         }
     };
 
-    // Each projection's products are summed in a fresh accumulator and then
-    // added to the total, highest projection first: the many small high-order
-    // terms meet the large low-order ones only as one partial sum each.
-    f32x16 tot[WM][WN], acc[WM][WN];
+    // One FP32 accumulator per output over the whole contraction, highest
+    // projection first: with an energy-compacting basis the small high-order
+    // products are summed before the large low-order ones.
+    f32x16 acc[WM][WN];
 #pragma unroll
     for (int a = 0; a < WM; ++a)
 #pragma unroll
         for (int b = 0; b < WN; ++b)
 #pragma unroll
-            for (int j = 0; j < 16; ++j) tot[a][b][j] = acc[a][b][j] = 0.0f;
+            for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
 
     auto step = [&](int64_t st, float (&la)[A_PER_T], f32x4 (&lb)[B_PER_T], const float (&sa)[A_PER_T],
                     const f32x4 (&sb)[B_PER_T]) {
@@ -308,17 +308,6 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[a][2], yf[b][2], acc[a][b], 0, 0, 0);
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[a][3], yf[b][3], acc[a][b], 0, 0, 0);
             }
-        if (st % kpl == kpl - 1) {
-#pragma unroll
-            for (int a = 0; a < WM; ++a)
-#pragma unroll
-                for (int b = 0; b < WN; ++b)
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) {
-                        tot[a][b][j] += acc[a][b][j];
-                        acc[a][b][j] = 0.0f;
-                    }
-        }
         if (st + 1 < nst) swrite(s ^ 1, sa, sb);
         __syncthreads();
     };
@@ -343,7 +332,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
                 const int64_t ar = a0 + (wm * WM + a) * 32 + 8 * (j >> 2) + 4 * g + (j & 3);
                 const int64_t bc = (tn * BNB + wn * WN + b) * 32 + row;
                 const int64_t m = ar * L + bc;
-                if (bc < L && m < nout) dst[m] = tot[a][b][j];
+                if (bc < L && m < nout) dst[m] = acc[a][b][j];
             }
 }
 
