@@ -249,8 +249,11 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     TIn* lds = reinterpret_cast<TIn*>(smem_raw);
 
-    const int64_t rti = tix / J.ngt;               // row tile of TRc rows
-    const int64_t j0 = (tix % J.ngt) * KB;
+    // tile order: along the groups of a row tile for row-contiguous sources;
+    // along the rows of a group tile for a transposed source, so that the
+    // workgroups in flight read neighbouring segments of the same k rows
+    const int64_t rti = J.trans ? tix % J.nrt : tix / J.ngt;          // row tile of TRc rows
+    const int64_t j0 = (J.trans ? tix / J.nrt : tix % J.ngt) * KB;
     const int64_t p0 = rti * TRc;
     const int64_t rbi = p0 / RB;                   // row block of the packed operand
     const int rib0 = (int)(p0 % RB);
@@ -376,9 +379,11 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                 }
             }
         } else {
+            // element loads (unaligned rows), kB per thread in flight before
+            // their LDS stores
             const int n1 = TRc * KB * TCp;
-            for (int idx = threadIdx.x; idx < n1; idx += kPackThreads) {
-                int rr, jj, tt;
+            constexpr int kB = 64 / (int)sizeof(TIn);
+            auto where = [&](int idx, int& rr, int& jj, int& tt) {
                 if (!J.trans) {
                     tt = idx % TCp;
                     const int q = idx / TCp;
@@ -390,11 +395,30 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                     tt = q % TCp;
                     jj = q / TCp;
                 }
-                const int64_t p = p0 + rr;
-                const int64_t k = (j0 + jj) * L + t0 + tt;
-                TIn v = (TIn)0;
-                if (tt < TC && p < J.P && k < J.K) v = J.trans ? X[k * J.ld + p] : X[p * J.ld + k];
-                lds[loff(rr, jj, tt)] = v;
+            };
+            for (int base = 0; base < n1; base += kB * kPackThreads) {
+                TIn v[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int idx = base + u * kPackThreads + (int)threadIdx.x;
+                    v[u] = (TIn)0;
+                    if (idx < n1) {
+                        int rr, jj, tt;
+                        where(idx, rr, jj, tt);
+                        const int64_t p = p0 + rr;
+                        const int64_t k = (j0 + jj) * L + t0 + tt;
+                        if (tt < TC && p < J.P && k < J.K) v[u] = J.trans ? X[k * J.ld + p] : X[p * J.ld + k];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int idx = base + u * kPackThreads + (int)threadIdx.x;
+                    if (idx < n1) {
+                        int rr, jj, tt;
+                        where(idx, rr, jj, tt);
+                        lds[loff(rr, jj, tt)] = v[u];
+                    }
+                }
             }
         }
     };
@@ -573,13 +597,14 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 
 // Two jobs passed by value (one GEMM's A and B sides).
 // Waves per SIMD the register allocation must allow for the matrix-core
-// variants with direct loads (32 KB rounds, so LDS admits 5 workgroups per
-// CU): 4 for FP32 output, 3 for the 16-bit outputs, whose conversions need
-// more registers; else the compiler's choice.
+// variants: with direct loads (32 KB rounds, so LDS admits 5 workgroups per
+// CU) 4 for FP32 output and 3 for the 16-bit outputs, whose conversions need
+// more registers; with register staging 2 (two workgroups per CU); else the
+// compiler's choice.
 template <typename TIn, int PREC, int RL, int NCH, bool DMA>
 constexpr int pack_waves_per_eu()
 {
-    if constexpr (DMA && pack_mfma<TIn, PREC, RL, NCH>()) return PREC == P_F32 ? 4 : 3;
+    if constexpr (pack_mfma<TIn, PREC, RL, NCH>()) return DMA ? (PREC == P_F32 ? 4 : 3) : 2;
     return 1;
 }
 
@@ -677,6 +702,12 @@ int launch_t(const PackArgs* a, int n, hipStream_t s)
     constexpr Layout ly = layout_of(PREC);
     PackJob<TIn> ja = make_job<TIn, PREC>(a[0]);
     PackJob<TIn> jb = n > 1 ? make_job<TIn, PREC>(a[1]) : ja;
+    if (n > 1 && ja.swz != jb.swz) {
+        // one side streams into LDS directly, the other needs register
+        // staging: two launches, each with its own staging
+        const int e = launch_t<TIn, PREC, RL, NCH>(a, 1, s);
+        return e != 0 ? e : launch_t<TIn, PREC, RL, NCH>(a + 1, 1, s);
+    }
     const int64_t na = ja.nrt * ja.ngt;
     const int64_t nb = n > 1 ? jb.nrt * jb.ngt : 0;
     const bool dma = ja.swz && jb.swz;
@@ -717,39 +748,59 @@ int launch_p(const PackArgs* a, int n, hipStream_t s)
 template <typename TIn, int PREC, int RL, int NCH>
 int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
 {
-    constexpr Layout ly = layout_of(PREC);
-    std::vector<PackJob<TIn>> jobs(n);
-    std::vector<int64_t> prefix(n + 1, 0);
-    bool dma = true;
-    for (int i = 0; i < n; ++i) {
-        jobs[i] = make_job<TIn, PREC>(a[i]);
-        prefix[i + 1] = prefix[i] + jobs[i].nrt * jobs[i].ngt;
-        dma = dma && jobs[i].swz;
-    }
-    size_t lds_e = 0;
-    for (int i = 0; i < n; ++i) lds_e = std::max(lds_e, round_lds_elems<TIn, PREC>(jobs[i], dma));
-    if (prefix[n] > 0x7fffffff || prefix[n] == 0) return -2;
-    char* t = (char*)table;
-    const size_t jb = sizeof(PackJob<TIn>) * n;
-    if (hipMemcpyAsync(t, jobs.data(), jb, hipMemcpyHostToDevice, s) != hipSuccess) return -1;
-    if (hipMemcpyAsync(t + rup(jb, 256), prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s) !=
-        hipSuccess)
-        return -1;
-    size_t lds = lds_e * sizeof(TIn);
-    if constexpr (pack_mfma<TIn, PREC, RL, NCH>())
-        lds = std::max(lds, (size_t)16 * pack_mfma_ds<PREC>() * sizeof(float));
-    (void)ly;
-    if constexpr (std::is_same<TIn, float>::value) {
-        if (dma) {
-            hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, true>), dim3((unsigned)prefix[n]),
-                               dim3(kPackThreads), lds, s, (const PackJob<TIn>*)t, (const int64_t*)(t + rup(jb, 256)),
-                               n);
-            return hipGetLastError() == hipSuccess ? 0 : -1;
+    // jobs with direct LDS loads first, then those with register staging:
+    // one launch per set, sharing the job array; the table holds the jobs
+    // and one prefix array per set
+    std::vector<PackJob<TIn>> jobs;
+    jobs.reserve(n);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < n; ++i) {
+            PackJob<TIn> j = make_job<TIn, PREC>(a[i]);
+            if ((j.swz != 0) == (pass == 0)) jobs.push_back(j);
         }
+    int nd = 0;
+    while (nd < n && jobs[nd].swz) ++nd;
+    std::vector<int64_t> prefix[2];
+    size_t lds_e[2] = {0, 0};
+    for (int set = 0; set < 2; ++set) {
+        const int j0 = set == 0 ? 0 : nd, j1 = set == 0 ? nd : n;
+        prefix[set].assign(j1 - j0 + 1, 0);
+        for (int i = j0; i < j1; ++i) {
+            prefix[set][i - j0 + 1] = prefix[set][i - j0] + jobs[i].nrt * jobs[i].ngt;
+            lds_e[set] = std::max(lds_e[set], round_lds_elems<TIn, PREC>(jobs[i], set == 0));
+        }
+        if (prefix[set].back() > 0x7fffffff) return -2;
     }
-    hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, false>), dim3((unsigned)prefix[n]),
-                       dim3(kPackThreads), lds, s, (const PackJob<TIn>*)t, (const int64_t*)(t + rup(jb, 256)), n);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    if (prefix[0].back() + prefix[1].back() == 0) return -2;
+    char* t = (char*)table;
+    const size_t jbytes = rup((int64_t)sizeof(PackJob<double>) * n, 256);
+    const size_t pbytes = rup(8 * (int64_t)(n + 1), 256);
+    if (hipMemcpyAsync(t, jobs.data(), sizeof(PackJob<TIn>) * n, hipMemcpyHostToDevice, s) != hipSuccess) return -1;
+    for (int set = 0; set < 2; ++set) {
+        const int j0 = set == 0 ? 0 : nd, j1 = set == 0 ? nd : n;
+        const int64_t grid = prefix[set].back();
+        if (grid == 0) continue;
+        char* pre = t + jbytes + set * pbytes;
+        if (hipMemcpyAsync(pre, prefix[set].data(), sizeof(int64_t) * prefix[set].size(), hipMemcpyHostToDevice,
+                           s) != hipSuccess)
+            return -1;
+        size_t lds = lds_e[set] * sizeof(TIn);
+        if constexpr (pack_mfma<TIn, PREC, RL, NCH>())
+            lds = std::max(lds, (size_t)16 * pack_mfma_ds<PREC>() * sizeof(float));
+        const PackJob<TIn>* jt = (const PackJob<TIn>*)t + j0;
+        if constexpr (std::is_same<TIn, float>::value) {
+            if (set == 0) {
+                hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, true>), dim3((unsigned)grid),
+                                   dim3(kPackThreads), lds, s, jt, (const int64_t*)pre, j1 - j0);
+                if (hipGetLastError() != hipSuccess) return -1;
+                continue;
+            }
+        }
+        hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, false>), dim3((unsigned)grid),
+                           dim3(kPackThreads), lds, s, jt, (const int64_t*)pre, j1 - j0);
+        if (hipGetLastError() != hipSuccess) return -1;
+    }
+    return 0;
 }
 
 template <typename TIn, int PREC>
@@ -789,7 +840,8 @@ int launch_pack(int prec, const PackArgs& a, hipStream_t s) { return launch_pack
 
 size_t pack_grouped_table_bytes(int n)
 {
-    return (size_t)rup((int64_t)sizeof(PackJob<double>) * n, 256) + (size_t)rup(8 * (int64_t)(n + 1), 256);
+    // the jobs, then two prefix arrays (direct-load and register-staged sets)
+    return (size_t)rup((int64_t)sizeof(PackJob<double>) * n, 256) + 2 * (size_t)rup(8 * (int64_t)(n + 1), 256);
 }
 
 int launch_pack_grouped(int prec, const PackArgs* a, int n, void* table, hipStream_t s)
