@@ -53,6 +53,7 @@ struct PackJob {
     // chunk c = group * TC / 4 + t / 4 at slot c ^ (rr & SM), so that the
     // 16 rows read by one matrix-core step fall in distinct banks.
     int swz, lnc, ltc4, sm;
+    int dma4;        // direct loads of single values (rows not 16-byte aligned)
 };
 
 // ---- OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits,
@@ -118,6 +119,12 @@ __device__ __forceinline__ void store_lane(char* __restrict__ out, int64_t off, 
 __device__ __forceinline__ void lds_direct16(const float* src, float* dst)
 {
     __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+}
+
+// 4 bytes per lane: lane i writes dst + i.
+__device__ __forceinline__ void lds_direct4(const float* src, float* dst)
+{
+    __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
 }
 
 template <typename TIn> struct Vec4;
@@ -281,9 +288,36 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
             // instruction filling 64 consecutive slots.  Chunks outside the
             // operand (rows >= P, indices >= K; K is a multiple of 4 here)
             // are read from X itself and then overwritten with zeros.
-            const int per_wave = (TRc << lnc) / kPackThreads;
             const bool interior = p0 + TRc <= J.P && (j0 + KB - 1) * L + t0 + TC <= J.K;
             const TIn* __restrict__ base = X + p0 * J.ld + j0 * L + t0;
+            if (J.dma4) {
+                // rows not 16-byte aligned: one value per lane, 64 consecutive
+                // floats of the layout per wave instruction (value e of chunk
+                // slot s at float 4 s + e), validity per value
+                const int per_wave4 = (TRc << lnc) * 4 / kPackThreads;
+                for (int i = 0; i < per_wave4; ++i) {
+                    const int f0 = (wave * per_wave4 + i) * 64;
+                    const int f = f0 + lane;
+                    const int rr = f >> (lnc + 2);
+                    const int c = ((f >> 2) & ((1 << lnc) - 1)) ^ (rr & sm);
+                    const int64_t ko = (c >> ltc4) * L + 4 * (c & ((1 << ltc4) - 1)) + (f & 3);
+                    const TIn* src = base + rr * J.ld + ko;
+                    if (!interior && (p0 + rr >= J.P || j0 * L + t0 + ko >= J.K)) src = X;
+                    lds_direct4(src, lds + f0);
+                }
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                if (!interior) {
+                    for (int i = 0; i < per_wave4; ++i) {
+                        const int f = (wave * per_wave4 + i) * 64 + lane;
+                        const int rr = f >> (lnc + 2);
+                        const int c = ((f >> 2) & ((1 << lnc) - 1)) ^ (rr & sm);
+                        const int64_t ko = (c >> ltc4) * L + 4 * (c & ((1 << ltc4) - 1)) + (f & 3);
+                        if (p0 + rr >= J.P || j0 * L + t0 + ko >= J.K) lds[f] = (TIn)0;
+                    }
+                }
+                return;
+            }
+            const int per_wave = (TRc << lnc) / kPackThreads;
             unsigned outside = 0;
             for (int i = 0; i < per_wave; ++i) {
                 const int slot0 = (wave * per_wave + i) * 64;
@@ -675,11 +709,13 @@ PackJob<TIn> make_job(const PackArgs& a)
     j.RS = ly.KB * j.JS + 4;
     // direct loads into the swizzled layout: FP32 rows contiguous along k,
     // TC / 4 a power of two, the tile's chunks filling whole 64-slot wave
-    // instructions (at most 32 per wave)
+    // instructions (at most 32 per wave); 16 bytes per lane when the rows are
+    // 16-byte aligned, else one value per lane
     const int tc4 = TC / 4;
     const int nc = ly.KB * tc4;
-    j.swz = std::is_same<TIn, float>::value && j.vec4 && !j.trans && tc4 > 0 && (tc4 & (tc4 - 1)) == 0 &&
+    j.swz = std::is_same<TIn, float>::value && !j.trans && TC % 4 == 0 && tc4 > 0 && (tc4 & (tc4 - 1)) == 0 &&
             (Cmap<PREC>::TRc * nc) % kPackThreads == 0 && Cmap<PREC>::TRc * nc <= 32 * kPackThreads;
+    j.dma4 = j.swz && !j.vec4;
     j.lnc = j.ltc4 = j.sm = 0;
     if (j.swz) {
         while ((1 << j.lnc) < nc) ++j.lnc;

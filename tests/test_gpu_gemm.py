@@ -133,7 +133,7 @@ def test_fp8_ragged(pg, prec):
     (64, 96, 96, 3, "custom"),      # L not a power of two
     (300, 512, 129, 256, "dct2"),   # the largest L
 ])
-@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("prec", ["f32", "f64", "bf16x3"])
 def test_ragged_shapes_all_r_edges(pg, M, K, W, L, kind, prec):
     rng = np.random.default_rng(M * 7 + K)
     A = rng.standard_normal((M, K))
