@@ -54,6 +54,10 @@ struct PackJob {
     // 16 rows read by one matrix-core step fall in distinct banks.
     int swz, lnc, ltc4, sm;
     int dma4;        // direct loads of single values (rows not 16-byte aligned)
+    // Transposed round layout (FP32 transposed source): element (rr, group
+    // jj, t) at (jj * TCp + t) * RT + rr, filled by single-value direct loads
+    // along the contiguous rows of the source.
+    int tdma, RT;
 };
 
 // ---- OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits,
@@ -242,7 +246,10 @@ __device__ __forceinline__ void store_fp8_quarter(char* __restrict__ out, int64_
     }
 }
 
-template <typename TIn, int PREC, int RL, int NCH, bool DMA>
+// LAY: round layout in LDS -- 0 padded rows (register staging), 1 swizzled
+// (direct loads, rows contiguous along k), 2 transposed (direct loads from a
+// transposed source).
+template <typename TIn, int PREC, int RL, int NCH, int LAY>
 __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 {
     constexpr Layout ly = layout_of(PREC);
@@ -276,13 +283,54 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
     // swizzled layout with direct loads, else rows of RS with padding
     const int lnc = J.lnc, ltc4 = J.ltc4, sm = J.sm;
     auto loff = [&](int rr, int jj, int t) -> int {
-        if constexpr (DMA) return ((rr << lnc) + (((jj << ltc4) + (t >> 2)) ^ (rr & sm))) * 4 + (t & 3);
+        if constexpr (LAY == 1) return ((rr << lnc) + (((jj << ltc4) + (t >> 2)) ^ (rr & sm))) * 4 + (t & 3);
+        else if constexpr (LAY == 2) return (jj * TCp + t) * J.RT + rr;
         else return rr * RS + jj * JS + t;
     };
 
     // staging of one round: t0 .. t0 + TC of every group of the tile into LDS
     auto stage = [&](int t0) {
-        if constexpr (DMA) {
+        if constexpr (LAY == 2) {
+            // transposed layout filled by single-value direct loads: 64
+            // consecutive floats per wave instruction, i.e. consecutive rows
+            // p of one source row k (coalesced); padding columns rr >= TRc
+            // and values outside the operand (p >= P, k >= K, t >= TC) are
+            // read from X itself and then overwritten with zeros
+            const int RT = J.RT;
+            const int tot = KB * TCp * RT;
+            const int per_wave = (tot + kPackThreads - 1) / kPackThreads;
+            const bool interior = p0 + TRc <= J.P && (j0 + KB - 1) * L + t0 + TC <= J.K && TC == TCp;
+            auto src_of = [&](int f, bool& ok) -> const TIn* {
+                const int q = f / RT, rr = f - q * RT;
+                const int jj = q / TCp, t = q - jj * TCp;
+                const int64_t p = p0 + rr;
+                const int64_t k = (j0 + jj) * L + t0 + t;
+                ok = rr < TRc && (interior || (t < TC && p < J.P && k < J.K));
+                return ok ? X + k * J.ld + p : X;
+            };
+            for (int i = 0; i < per_wave; ++i) {
+                const int f0 = (wave * per_wave + i) * 64;
+                const int f = f0 + lane;
+                if (f0 < tot) {
+                    bool ok;
+                    const TIn* src = src_of(f < tot ? f : tot - 1, ok);
+                    if (f < tot) lds_direct4(src, lds + f0);
+                }
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (!interior) {
+                for (int i = 0; i < per_wave; ++i) {
+                    const int f = (wave * per_wave + i) * 64 + lane;
+                    if (f < tot) {
+                        bool ok;
+                        src_of(f, ok);
+                        if (!ok) lds[f] = (TIn)0;
+                    }
+                }
+            }
+            return;
+        }
+        if constexpr (LAY == 1) {
             // swizzled layout filled by direct loads: the 16-byte chunks go
             // from memory straight into LDS (no registers), each wave
             // instruction filling 64 consecutive slots.  Chunks outside the
@@ -490,10 +538,12 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 #pragma unroll
             for (int gi = 0; gi < GPW; ++gi) {
                 const int jj = wave * GPW + gi;
-                ay[gi] = DMA ? (((jj << ltc4) ^ (i16 & sm)) ^ kq) : kq;
+                ay[gi] = LAY == 1 ? (((jj << ltc4) ^ (i16 & sm)) ^ kq) : kq;
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
-                    ab[gi][h] = DMA ? lds + (((h * 16 + i16) << lnc) << 2) : lds + (h * 16 + i16) * RS + jj * JS;
+                    ab[gi][h] = LAY == 1   ? lds + (((h * 16 + i16) << lnc) << 2)
+                                : LAY == 2 ? lds + (jj * TCp + 4 * kq) * J.RT + h * 16 + i16
+                                           : lds + (h * 16 + i16) * RS + jj * JS;
             }
             const int lcol = min(lp + i16, L - 1);     // columns >= r are never stored
             for (int t0 = 0; t0 < L; t0 += TC) {
@@ -518,8 +568,15 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                     for (int gi = 0; gi < GPW; ++gi)
 #pragma unroll
                         for (int h = 0; h < 2; ++h)
-                            d[gi][h] = ok ? *reinterpret_cast<const f32x4*>(ab[gi][h] + 4 * (ay[gi] ^ (4 * q)))
-                                          : f32x4{0.f, 0.f, 0.f, 0.f};
+                            if constexpr (LAY == 2) {
+                                // the 4 indices of the chunk are rows RT apart
+                                const TIn* pp = ab[gi][h] + 16 * q * J.RT;
+                                d[gi][h] = ok ? f32x4{pp[0], pp[J.RT], pp[2 * J.RT], pp[3 * J.RT]}
+                                              : f32x4{0.f, 0.f, 0.f, 0.f};
+                            } else {
+                                d[gi][h] = ok ? *reinterpret_cast<const f32x4*>(ab[gi][h] + 4 * (ay[gi] ^ (4 * q)))
+                                              : f32x4{0.f, 0.f, 0.f, 0.f};
+                            }
                 };
                 rdq(0, av[0]);
 #pragma unroll
@@ -582,7 +639,13 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                     }
 #pragma unroll
                     for (int e = 0; e < Ec; ++e) {
-                        const V4 v = *reinterpret_cast<const V4*>(lds + loff(row, g * Ec + e, 4 * tt4));
+                        V4 v;
+                        if constexpr (LAY == 2) {
+                            const TIn* pp = lds + loff(row, g * Ec + e, 4 * tt4);
+                            v = V4{pp[0], pp[J.RT], pp[2 * J.RT], pp[3 * J.RT]};
+                        } else {
+                            v = *reinterpret_cast<const V4*>(lds + loff(row, g * Ec + e, 4 * tt4));
+                        }
 #pragma unroll
                         for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -631,30 +694,34 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
 
 // Two jobs passed by value (one GEMM's A and B sides).
 // Waves per SIMD the register allocation must allow for the matrix-core
-// variants: with direct loads (32 KB rounds, so LDS admits 5 workgroups per
-// CU) 4 for FP32 output and 3 for the 16-bit outputs, whose conversions need
-// more registers; with register staging 2 (two workgroups per CU); else the
-// compiler's choice.
-template <typename TIn, int PREC, int RL, int NCH, bool DMA>
+// variants: with direct loads (rounds of at most 48 KB) 4 for FP32 output and
+// 3 for the 16-bit outputs, whose conversions need more registers (2 for the
+// two-job launch of a transposed source, which needs more still); with
+// register staging 2; else the compiler's choice.
+template <typename TIn, int PREC, int RL, int NCH, int LAY, bool GROUPED>
 constexpr int pack_waves_per_eu()
 {
-    if constexpr (pack_mfma<TIn, PREC, RL, NCH>()) return DMA ? (PREC == P_F32 ? 4 : 3) : 2;
+    if constexpr (pack_mfma<TIn, PREC, RL, NCH>()) {
+        if constexpr (LAY == 0) return 2;
+        if constexpr (PREC == P_F32) return 4;
+        return LAY == 2 && !GROUPED ? 2 : 3;
+    }
     return 1;
 }
 
-template <typename TIn, int PREC, int RL, int NCH, bool DMA>
+template <typename TIn, int PREC, int RL, int NCH, int LAY>
 __global__ __launch_bounds__(kPackThreads)
-__attribute__((amdgpu_waves_per_eu(pack_waves_per_eu<TIn, PREC, RL, NCH, DMA>()))) void pack_kernel(PackJob<TIn> ja, PackJob<TIn> jb, int64_t nblk_a)
+__attribute__((amdgpu_waves_per_eu(pack_waves_per_eu<TIn, PREC, RL, NCH, LAY, false>()))) void pack_kernel(PackJob<TIn> ja, PackJob<TIn> jb, int64_t nblk_a)
 {
-    if ((int64_t)blockIdx.x < nblk_a) pack_tile<TIn, PREC, RL, NCH, DMA>(ja, (int64_t)blockIdx.x);
-    else pack_tile<TIn, PREC, RL, NCH, DMA>(jb, (int64_t)blockIdx.x - nblk_a);
+    if ((int64_t)blockIdx.x < nblk_a) pack_tile<TIn, PREC, RL, NCH, LAY>(ja, (int64_t)blockIdx.x);
+    else pack_tile<TIn, PREC, RL, NCH, LAY>(jb, (int64_t)blockIdx.x - nblk_a);
 }
 
 // Any number of jobs from a device table; prefix[i] is the first workgroup
 // of job i (prefix[njobs] = grid size).
-template <typename TIn, int PREC, int RL, int NCH, bool DMA>
+template <typename TIn, int PREC, int RL, int NCH, int LAY>
 __global__ __launch_bounds__(kPackThreads)
-__attribute__((amdgpu_waves_per_eu(pack_waves_per_eu<TIn, PREC, RL, NCH, DMA>()))) void pack_grouped_kernel(const PackJob<TIn>* __restrict__ jobs,
+__attribute__((amdgpu_waves_per_eu(pack_waves_per_eu<TIn, PREC, RL, NCH, LAY, true>()))) void pack_grouped_kernel(const PackJob<TIn>* __restrict__ jobs,
                                                                     const int64_t* __restrict__ prefix, int njobs)
 {
     const int64_t b = blockIdx.x;
@@ -664,7 +731,7 @@ __attribute__((amdgpu_waves_per_eu(pack_waves_per_eu<TIn, PREC, RL, NCH, DMA>())
         if (prefix[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    pack_tile<TIn, PREC, RL, NCH, DMA>(jobs[lo], b - prefix[lo]);
+    pack_tile<TIn, PREC, RL, NCH, LAY>(jobs[lo], b - prefix[lo]);
 }
 
 template <typename TIn, int PREC>
@@ -722,46 +789,71 @@ PackJob<TIn> make_job(const PackArgs& a)
         while ((1 << j.ltc4) < tc4) ++j.ltc4;
         j.sm = (nc < 16 ? nc : 16) - 1;
     }
+    // transposed FP32 sources whose rows are not 16-byte aligned (aligned
+    // ones are faster with 16-byte register staging), 32-row tiles: direct
+    // loads into the transposed layout when its round (columns padded to
+    // TRc + 4) fits the LDS budget
+    j.RT = Cmap<PREC>::TRc + 4;
+    j.tdma = std::is_same<TIn, float>::value && j.trans && !j.vec4 && Cmap<PREC>::TRc == 32 &&
+             (size_t)ly.KB * j.TCp * j.RT * sizeof(TIn) <= (size_t)kPackLdsBytes;
     return j;
 }
 
-// LDS floats (or doubles) of one staged round.
+// Round layout of a job (the LAY of pack_tile) and its LDS elements.
+template <typename TIn>
+int job_layout(const PackJob<TIn>& j) { return j.swz ? 1 : (j.tdma ? 2 : 0); }
+
 template <typename TIn, int PREC>
-size_t round_lds_elems(const PackJob<TIn>& j, bool dma)
+size_t round_lds_elems(const PackJob<TIn>& j, int lay)
 {
-    return (size_t)Cmap<PREC>::TRc * (dma ? ((size_t)4 << j.lnc) : (size_t)j.RS);
+    if (lay == 1) return (size_t)Cmap<PREC>::TRc * ((size_t)4 << j.lnc);
+    if (lay == 2) return (size_t)layout_of(PREC).KB * j.TCp * j.RT;
+    return (size_t)Cmap<PREC>::TRc * j.RS;
+}
+
+// Launch of pack_kernel (one or two jobs) or pack_grouped_kernel with the
+// round layout chosen at run time.
+template <typename TIn, int PREC, int RL, int NCH, bool GROUPED, int LAY, typename... Args>
+void launch_one(dim3 grid, size_t lds, hipStream_t s, Args... args)
+{
+    if constexpr (GROUPED)
+        hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, LAY>), grid, dim3(kPackThreads), lds, s, args...);
+    else
+        hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH, LAY>), grid, dim3(kPackThreads), lds, s, args...);
+}
+
+template <typename TIn, int PREC, int RL, int NCH, bool GROUPED, typename... Args>
+int launch_lay(int lay, dim3 grid, size_t lds, hipStream_t s, Args... args)
+{
+    if constexpr (std::is_same<TIn, float>::value) {
+        if (lay == 1) launch_one<TIn, PREC, RL, NCH, GROUPED, 1>(grid, lds, s, args...);
+        else if (lay == 2) launch_one<TIn, PREC, RL, NCH, GROUPED, 2>(grid, lds, s, args...);
+        else launch_one<TIn, PREC, RL, NCH, GROUPED, 0>(grid, lds, s, args...);
+    } else {
+        (void)lay;
+        launch_one<TIn, PREC, RL, NCH, GROUPED, 0>(grid, lds, s, args...);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename TIn, int PREC, int RL, int NCH>
 int launch_t(const PackArgs* a, int n, hipStream_t s)
 {
-    constexpr Layout ly = layout_of(PREC);
     PackJob<TIn> ja = make_job<TIn, PREC>(a[0]);
     PackJob<TIn> jb = n > 1 ? make_job<TIn, PREC>(a[1]) : ja;
-    if (n > 1 && ja.swz != jb.swz) {
-        // one side streams into LDS directly, the other needs register
-        // staging: two launches, each with its own staging
+    const int lay = job_layout(ja);
+    if (n > 1 && job_layout(jb) != lay) {
+        // the two sides stage differently: one launch each
         const int e = launch_t<TIn, PREC, RL, NCH>(a, 1, s);
         return e != 0 ? e : launch_t<TIn, PREC, RL, NCH>(a + 1, 1, s);
     }
     const int64_t na = ja.nrt * ja.ngt;
     const int64_t nb = n > 1 ? jb.nrt * jb.ngt : 0;
-    const bool dma = ja.swz && jb.swz;
-    size_t lds = std::max(round_lds_elems<TIn, PREC>(ja, dma), round_lds_elems<TIn, PREC>(jb, dma)) * sizeof(TIn);
+    size_t lds = std::max(round_lds_elems<TIn, PREC>(ja, lay), round_lds_elems<TIn, PREC>(jb, lay)) * sizeof(TIn);
     if constexpr (pack_mfma<TIn, PREC, RL, NCH>())
         lds = std::max(lds, (size_t)16 * pack_mfma_ds<PREC>() * sizeof(float));
-    (void)ly;
     if (na + nb > 0x7fffffff) return -2;
-    if constexpr (std::is_same<TIn, float>::value) {
-        if (dma) {
-            hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH, true>), dim3((unsigned)(na + nb)), dim3(kPackThreads),
-                               lds, s, ja, jb, na);
-            return hipGetLastError() == hipSuccess ? 0 : -1;
-        }
-    }
-    hipLaunchKernelGGL((pack_kernel<TIn, PREC, RL, NCH, false>), dim3((unsigned)(na + nb)), dim3(kPackThreads), lds, s,
-                       ja, jb, na);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    return launch_lay<TIn, PREC, RL, NCH, false>(lay, dim3((unsigned)(na + nb)), lds, s, ja, jb, na);
 }
 
 template <typename TIn, int PREC>
@@ -784,57 +876,52 @@ int launch_p(const PackArgs* a, int n, hipStream_t s)
 template <typename TIn, int PREC, int RL, int NCH>
 int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
 {
-    // jobs with direct LDS loads first, then those with register staging:
-    // one launch per set, sharing the job array; the table holds the jobs
-    // and one prefix array per set
+    // jobs ordered by round layout (swizzled, transposed, padded): one launch
+    // per layout present, sharing the job array; the table holds the jobs
+    // and one prefix array per layout
     std::vector<PackJob<TIn>> jobs;
     jobs.reserve(n);
-    for (int pass = 0; pass < 2; ++pass)
+    int start[4] = {0, 0, 0, 0};
+    const int order[3] = {1, 2, 0};
+    for (int o = 0; o < 3; ++o) {
+        start[o] = (int)jobs.size();
         for (int i = 0; i < n; ++i) {
             PackJob<TIn> j = make_job<TIn, PREC>(a[i]);
-            if ((j.swz != 0) == (pass == 0)) jobs.push_back(j);
+            if (job_layout(j) == order[o]) jobs.push_back(j);
         }
-    int nd = 0;
-    while (nd < n && jobs[nd].swz) ++nd;
-    std::vector<int64_t> prefix[2];
-    size_t lds_e[2] = {0, 0};
-    for (int set = 0; set < 2; ++set) {
-        const int j0 = set == 0 ? 0 : nd, j1 = set == 0 ? nd : n;
-        prefix[set].assign(j1 - j0 + 1, 0);
-        for (int i = j0; i < j1; ++i) {
-            prefix[set][i - j0 + 1] = prefix[set][i - j0] + jobs[i].nrt * jobs[i].ngt;
-            lds_e[set] = std::max(lds_e[set], round_lds_elems<TIn, PREC>(jobs[i], set == 0));
-        }
-        if (prefix[set].back() > 0x7fffffff) return -2;
     }
-    if (prefix[0].back() + prefix[1].back() == 0) return -2;
+    start[3] = n;
+    std::vector<int64_t> prefix[3];
+    size_t lds_e[3] = {0, 0, 0};
+    int64_t total = 0;
+    for (int o = 0; o < 3; ++o) {
+        prefix[o].assign(start[o + 1] - start[o] + 1, 0);
+        for (int i = start[o]; i < start[o + 1]; ++i) {
+            prefix[o][i - start[o] + 1] = prefix[o][i - start[o]] + jobs[i].nrt * jobs[i].ngt;
+            lds_e[o] = std::max(lds_e[o], round_lds_elems<TIn, PREC>(jobs[i], order[o]));
+        }
+        if (prefix[o].back() > 0x7fffffff) return -2;
+        total += prefix[o].back();
+    }
+    if (total == 0) return -2;
     char* t = (char*)table;
     const size_t jbytes = rup((int64_t)sizeof(PackJob<double>) * n, 256);
     const size_t pbytes = rup(8 * (int64_t)(n + 1), 256);
     if (hipMemcpyAsync(t, jobs.data(), sizeof(PackJob<TIn>) * n, hipMemcpyHostToDevice, s) != hipSuccess) return -1;
-    for (int set = 0; set < 2; ++set) {
-        const int j0 = set == 0 ? 0 : nd, j1 = set == 0 ? nd : n;
-        const int64_t grid = prefix[set].back();
+    for (int o = 0; o < 3; ++o) {
+        const int64_t grid = prefix[o].back();
         if (grid == 0) continue;
-        char* pre = t + jbytes + set * pbytes;
-        if (hipMemcpyAsync(pre, prefix[set].data(), sizeof(int64_t) * prefix[set].size(), hipMemcpyHostToDevice,
-                           s) != hipSuccess)
+        char* pre = t + jbytes + o * pbytes;
+        if (hipMemcpyAsync(pre, prefix[o].data(), sizeof(int64_t) * prefix[o].size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
             return -1;
-        size_t lds = lds_e[set] * sizeof(TIn);
+        size_t lds = lds_e[o] * sizeof(TIn);
         if constexpr (pack_mfma<TIn, PREC, RL, NCH>())
             lds = std::max(lds, (size_t)16 * pack_mfma_ds<PREC>() * sizeof(float));
-        const PackJob<TIn>* jt = (const PackJob<TIn>*)t + j0;
-        if constexpr (std::is_same<TIn, float>::value) {
-            if (set == 0) {
-                hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, true>), dim3((unsigned)grid),
-                                   dim3(kPackThreads), lds, s, jt, (const int64_t*)pre, j1 - j0);
-                if (hipGetLastError() != hipSuccess) return -1;
-                continue;
-            }
-        }
-        hipLaunchKernelGGL((pack_grouped_kernel<TIn, PREC, RL, NCH, false>), dim3((unsigned)grid),
-                           dim3(kPackThreads), lds, s, jt, (const int64_t*)pre, j1 - j0);
-        if (hipGetLastError() != hipSuccess) return -1;
+        const int e = launch_lay<TIn, PREC, RL, NCH, true>(order[o], dim3((unsigned)grid), lds, s,
+                                                           (const PackJob<TIn>*)t + start[o], (const int64_t*)pre,
+                                                           start[o + 1] - start[o]);
+        if (e != 0) return e;
     }
     return 0;
 }
@@ -876,8 +963,8 @@ int launch_pack(int prec, const PackArgs& a, hipStream_t s) { return launch_pack
 
 size_t pack_grouped_table_bytes(int n)
 {
-    // the jobs, then two prefix arrays (direct-load and register-staged sets)
-    return (size_t)rup((int64_t)sizeof(PackJob<double>) * n, 256) + 2 * (size_t)rup(8 * (int64_t)(n + 1), 256);
+    // the jobs, then one prefix array per round layout
+    return (size_t)rup((int64_t)sizeof(PackJob<double>) * n, 256) + 3 * (size_t)rup(8 * (int64_t)(n + 1), 256);
 }
 
 int launch_pack_grouped(int prec, const PackArgs* a, int n, void* table, hipStream_t s)
