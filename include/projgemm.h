@@ -153,8 +153,10 @@ int pj_pack_a(pj_basis b, int rmax, char transA, int M, int K, const void* A, in
 int pj_pack_b(pj_basis b, int rmax, char transB, int W, int K, const void* B, int64_t ldb,
               int prec, void* packed, size_t packed_bytes, void* stream);
 
-/* Packs both sides in ONE launch (same arguments as pj_pack_a and pj_pack_b
- * together); the small side overlaps with the large one. */
+/* Packs both sides in one launch (same arguments as pj_pack_a and pj_pack_b
+ * together); the small side overlaps with the large one.  Two launches when
+ * the sides need different staging (e.g. one row-contiguous, one
+ * transposed with unaligned rows). */
 int pj_pack_ab(pj_basis b, int rmax, char transA, char transB, int M, int W, int K,
                const void* A, int64_t lda, const void* B, int64_t ldb, int prec,
                void* Ap, size_t a_bytes, void* Bp, size_t b_bytes, void* stream);
@@ -214,10 +216,12 @@ size_t pj_gemm_batched_workspace_bytes(int count, const pj_gemm_desc* problems, 
                                        int tile_cfg);
 
 /* Many independent projected GEMMs of any sizes sharing one basis, r and
- * precision (paper Sec. III-B applied to each problem): ONE launch projects
- * and packs every A and B side, and ONE persistent launch computes every
- * (problem, output tile) item, the items sorted by decreasing contraction
- * length and dealt round-robin over a grid sized to the device.
+ * precision (paper Sec. III-B applied to each problem): one grouped launch
+ * per operand staging mode (at most three: rows streamed straight into LDS,
+ * transposed rows streamed into LDS, register staging) projects and packs
+ * every A and B side, and ONE persistent launch computes every (problem,
+ * output tile) item, the items sorted by decreasing contraction length and
+ * dealt round-robin over a grid sized to the device.
  *   problems : host array of `count` descriptors (device pointers inside).
  *   tile_cfg : workgroup tile as in pj_gemm_packed (-1: built-in choice);
  *              the autotuner picks it per batch.

@@ -402,8 +402,9 @@ def gemm_batched_workspace_bytes(descs, L: int, r: int, prec="f32", tile_cfg=-1)
 
 def gemm_batched(As, Bs, r: int, basis: Basis, prec="bf16", transA=False, transB=False, outs=None, beta=0.0,
                  tile_cfg=-1, workspace=None, stream=None):
-    """R_i = A_i Q_{r,K_i} B_i for every problem i, in one grouped pack launch
-    and one persistent GEMM launch.  Returns the list of outputs."""
+    """R_i = A_i Q_{r,K_i} B_i for every problem i, in grouped pack launches
+    (one per operand staging mode) and one persistent GEMM launch.  Returns
+    the list of outputs."""
     import torch
     if outs is None:
         outs = []
