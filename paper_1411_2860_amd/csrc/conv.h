@@ -9,7 +9,7 @@ namespace pj {
 // Projected cross-correlation (conv.hip).
 struct ConvGeom {
     int64_t nout;      // W - N + 1 valid outputs
-    int64_t nc, ncp;   // kernel phases per projection (N + L - 2) / L + 1, padded to 8
+    int64_t nc, ncp;   // kernel phases per projection (N + L - 2) / L + 1, padded to 4
     int64_t rows;      // output rows a (outputs m = a L + b)
     int64_t tiles_m;   // row tiles of the reduced cross-correlation
     int64_t nbp;       // length of each projected-signal row

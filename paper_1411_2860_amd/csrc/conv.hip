@@ -198,13 +198,15 @@ __global__ __launch_bounds__(256) void zero16_kernel(f32x4* __restrict__ p, int6
 
 // ---- step 3: the reduced cross-correlation ------------------------------------
 // Workgroup tile: BM output rows a x BN phases b, for one contiguous range of
-// projections [l_lo, l_hi) (the split; several splits raise the number of
-// workgroups when the tiles alone do not fill the chip).  Per k-block (8
-// consecutive kernel blocks c of one projection l) the workgroup stages in
-// LDS the Hankel window sc_l[a0 + c0 .. a0 + c0 + BM + 8) and the BN x 8
+// k-blocks (the split; several splits raise the number of workgroups when
+// the tiles alone do not fill the chip).  The contraction
+// index is kk = l ncp + c (ncp a multiple of 4), in k-blocks of 8: each half
+// (4 consecutive kernel blocks c0 .. c0 + 3 of one projection l) has its own
+// Hankel window sc_l[a0 + c0 .. a0 + c0 + BM + 4) in LDS, next to the BN x 8
 // slice of the packed kernel operand, double buffered, one barrier per
-// k-block.  A lane's A fragment is sc_l[a + c0 + 4g + e], e < 4 (rows
-// a = lane % 32 of the block, g = lane / 32), matching the packed B lanes.
+// k-block.  A lane's A fragment is sc_l[a + c0 + e], e < 4, from the window
+// of its half g = lane / 32 (rows a = lane % 32 of the block), matching the
+// packed B lanes.
 template <int WM, int WN, int WAVES_M, int WAVES_N>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
     const float* __restrict__ sc, int64_t nbp, const char* __restrict__ Kp, int64_t k_nrb, int64_t k_nkb,
@@ -214,12 +216,12 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
     constexpr int NT = 64 * WAVES_M * WAVES_N;
     constexpr int BMB = WM * WAVES_M, BNB = WN * WAVES_N;
     constexpr int BM = 32 * BMB;
-    constexpr int AW = BM + 8;
+    constexpr int AW = BM + 4;                      // window of one half k-block
     constexpr int NCH = BNB * 64;
     constexpr int B_PER_T = (NCH + NT - 1) / NT;
-    constexpr int A_PER_T = (AW + NT - 1) / NT;
+    constexpr int A_PER_T = (2 * AW + NT - 1) / NT;
     __shared__ __align__(16) f32x4 Bs[2][NCH];
-    __shared__ float As[2][AW];
+    __shared__ float As[2][2 * AW];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -227,9 +229,9 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
     const int wm = wave % WAVES_M, wn = wave / WAVES_M;
     const int64_t tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
     const int sp = blockIdx.y;
-    const int l_lo = (int)((int64_t)r * sp / nsplit), l_hi = (int)((int64_t)r * (sp + 1) / nsplit);
-    const int64_t kpl = ncp / 8;
-    const int64_t nst = (int64_t)(l_hi - l_lo) * kpl;
+    const int64_t kkt = (int64_t)r * ncp;                  // valid contraction indices
+    const int64_t kb_lo = k_nkb * sp / nsplit, kb_hi = k_nkb * (sp + 1) / nsplit;
+    const int64_t nst = kb_hi - kb_lo;
     const int64_t a0 = tm * BM;
     const int row = lane & 31, g = lane >> 5;
 
@@ -248,16 +250,31 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
     // contracted (two k-blocks of work to hide each global load behind)
     f32x4 bst0[B_PER_T], bst1[B_PER_T];
     float ast0[A_PER_T], ast1[A_PER_T];
-    // step st: projection l = l_hi - 1 - st / kpl (highest first), kernel blocks c0 = 8 (st % kpl)
+    // step st: k-block kb = kb_hi - 1 - st (highest projections first); half
+    // g holds indices kk = 8 kb + 4 g .. + 3 (zeros past r ncp).  The steps
+    // are loaded in order, so each staged value tracks its (l, c0) by
+    // stepping kk down by 8.
+    int64_t tkk[A_PER_T], tl[A_PER_T], tc[A_PER_T];
+#pragma unroll
+    for (int i = 0; i < A_PER_T; ++i) {
+        const int x = tid + i * NT;
+        tkk[i] = 8 * (kb_hi - 1) + 4 * (x >= AW ? 1 : 0);
+        tl[i] = tkk[i] >= 0 ? tkk[i] / ncp : 0;
+        tc[i] = tkk[i] - tl[i] * ncp;
+    }
     auto gload = [&](int64_t st, float (&ast)[A_PER_T], f32x4 (&bst)[B_PER_T]) {
-        const int64_t l = l_hi - 1 - st / kpl;
-        const int64_t cblk = st % kpl;
-        const int64_t kb = l * kpl + cblk;
-        const float* ap = sc + l * nbp + a0 + cblk * 8;
+        const int64_t kb = kb_hi - 1 - st;
 #pragma unroll
         for (int i = 0; i < A_PER_T; ++i) {
             const int x = tid + i * NT;
-            ast[i] = x < AW ? ap[x] : 0.0f;
+            const int xi = x >= AW ? x - AW : x;
+            ast[i] = x < 2 * AW && tkk[i] < kkt ? sc[tl[i] * nbp + a0 + tc[i] + xi] : 0.0f;
+            tkk[i] -= 8;
+            tc[i] -= 8;
+            while (tc[i] < 0 && tl[i] > 0) {
+                tc[i] += ncp;
+                --tl[i];
+            }
         }
 #pragma unroll
         for (int i = 0; i < B_PER_T; ++i)
@@ -267,7 +284,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
 #pragma unroll
         for (int i = 0; i < A_PER_T; ++i) {
             const int x = tid + i * NT;
-            if (x < AW) As[s][x] = ast[i];
+            if (x < 2 * AW) As[s][x] = ast[i];
         }
 #pragma unroll
         for (int i = 0; i < B_PER_T; ++i) {
@@ -294,7 +311,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void xcorr_kernel(
         f32x4 xf[WM], yf[WN];
 #pragma unroll
         for (int a = 0; a < WM; ++a) {
-            const float* p = &As[s][(wm * WM + a) * 32 + row + 4 * g];
+            const float* p = &As[s][g * AW + (wm * WM + a) * 32 + row];
             xf[a] = f32x4{p[0], p[1], p[2], p[3]};
         }
 #pragma unroll
@@ -474,12 +491,12 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
     ConvGeom g;
     g.nout = W - N + 1;
     g.nc = (N + L - 2) / L + 1;
-    g.ncp = rup(g.nc, 8);
+    g.ncp = rup(g.nc, 4);
     g.rows = cdiv(g.nout, L);                       // output rows a
     g.tiles_m = cdiv(g.rows, XBM);
     g.nbp = rup(g.tiles_m * XBM + g.ncp, 64);       // projected-signal row length
     g.k_nrb = cdiv(L, 32);
-    g.k_nkb = (int64_t)r * g.ncp / 8;
+    g.k_nkb = cdiv((int64_t)r * g.ncp, 8);
     const int bnb = L > 128 ? 8 : 4;
     g.tiles_n = cdiv(g.k_nrb, bnb);
     g.small = L <= kSmallL;
@@ -540,7 +557,8 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
     }
     // step 2
     {
-        if (a.L % 32 != 0) {
+        if (a.L % 32 != 0 || ((int64_t)a.r * g.ncp) % 8 != 0) {
+            // padding rows b >= L, or the unused half of the last k-block
             const int64_t n16 = g.k_nrb * g.k_nkb * 64;
             hipLaunchKernelGGL(zero16_kernel, dim3((unsigned)cdiv(n16, 256)), dim3(256), 0, st, (f32x4*)kp, n16);
             if (hipGetLastError() != hipSuccess) return -1;
