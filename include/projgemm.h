@@ -44,7 +44,7 @@ typedef enum {
     PJ_OK = 0,
     PJ_ERR_ARG = -1,          /* null pointer, bad enum, r or L out of range   */
     PJ_ERR_SHAPE = -2,        /* non-positive size, leading dimension too small */
-    PJ_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement    */
+    PJ_ERR_UNSUPPORTED = -3,  /* valid request the library does not implement   */
     PJ_ERR_WORKSPACE = -4,    /* workspace missing or smaller than the query    */
     PJ_ERR_SINGULAR = -5,     /* custom projection matrix is not invertible     */
     PJ_ERR_HIP = -6           /* a HIP runtime call or kernel launch failed     */
