@@ -480,8 +480,11 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ y
 // tile shapes: 128 x 256 (8 waves) when L > 128, else 128 x 128 (4 waves)
 constexpr int XW_M = 2, XW_N = 2, XWAVES_M = 2;
 constexpr int XBM = 32 * XW_M * XWAVES_M;
-constexpr int kXcorrTargetWG = 512;    // workgroups to aim for with splits
-constexpr int kXcorrMinSteps = 64;     // fewest k-blocks per split
+// Splits of the contraction: enough for one workgroup per CU (256) with at
+// least 32 k-blocks each, and up to 512 workgroups with at least 64 each
+// (more splits cost a pass over their partial outputs).
+constexpr int kXcorrFillWG = 256, kXcorrFillSteps = 32;
+constexpr int kXcorrTargetWG = 512, kXcorrMinSteps = 64;
 
 }  // namespace
 
@@ -501,8 +504,10 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
     g.tiles_n = cdiv(g.k_nrb, bnb);
     g.small = L <= kSmallL;
     const int64_t tiles = g.tiles_m * g.tiles_n;
-    int64_t ns = std::max<int64_t>(1, kXcorrTargetWG / std::max<int64_t>(1, tiles));
-    ns = std::min<int64_t>(ns, std::max<int64_t>(1, g.k_nkb / kXcorrMinSteps));
+    const int64_t t1 = std::max<int64_t>(1, tiles);
+    const int64_t fill = std::min<int64_t>(cdiv(kXcorrFillWG, t1), g.k_nkb / kXcorrFillSteps);
+    const int64_t more = std::min<int64_t>(kXcorrTargetWG / t1, g.k_nkb / kXcorrMinSteps);
+    int64_t ns = std::max<int64_t>(1, std::max(fill, more));
     ns = std::min<int64_t>(ns, r);
     g.nsplit = g.small ? 1 : (int)ns;
     g.sc_bytes = rup((int64_t)r * g.nbp * 4, 256);
