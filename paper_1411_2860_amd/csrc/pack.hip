@@ -33,6 +33,7 @@ namespace {
 
 constexpr int kPackThreads = 256;
 constexpr int kPackLdsBytes = 48 * 1024;
+constexpr int kPackSwzLdsBytes = 64 * 1024;
 
 template <typename TIn>
 struct PackJob {
@@ -769,6 +770,16 @@ PackJob<TIn> make_job(const PackArgs& a)
     };
     int TC = a.L;
     while (TC > 1 && (lds_of(TC) > (size_t)kPackLdsBytes || a.L % TC != 0 || (j.vec4 && TC % 4 != 0))) --TC;
+    if (std::is_same<TIn, float>::value && !a.trans && Cmap<PREC>::TRc == 32 && (ly.KB == 16 || a.r > 16)) {
+        // rows streamed into the unpadded swizzled layout: a larger budget
+        // (fewer rounds) for the 16-bit outputs and for passes over more
+        // than 16 projections; FP32 at r <= 16 keeps more workgroups per CU
+        int tc = 4;
+        while (tc * 2 <= a.L && a.L % (tc * 2) == 0 &&
+               (size_t)Cmap<PREC>::TRc * ly.KB * (tc * 2) * sizeof(TIn) <= (size_t)kPackSwzLdsBytes)
+            tc *= 2;
+        if (a.L % tc == 0 && tc > TC) TC = tc;
+    }
     if (j.vec4 && TC % 4 != 0) j.vec4 = 0;
     j.TC = TC;
     j.TCp = (TC + 3) / 4 * 4;
