@@ -209,7 +209,7 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.loads(f.read().split("```json", 1)[1].split("```", 1)[0])
-        if tr.get("sources_hash") == kernel_sources_hash() and tr.get("r") == r:
+        if tr.get("sources_hash") == kernel_sources_hash() and tr.get("r") == r and tr.get("tile_cfg") == cfg:
             traffic = tr.get("gemm_bytes_per_launch")
 
     out = {

@@ -119,9 +119,17 @@ def tune_gemm(M: int, W: int, K: int, L: int, r: int, prec: str = "f32", reps: i
     times = {}
     for i, _ in enumerate(pg.tile_configs(prec)):
         times[i] = _time_ms(lambda: pg.gemm_packed(Ap, Bp, r, M, W, K, L, r, r, prec=prec, out=R, tile_cfg=i), reps)
-    best = min(times, key=times.get)
+    best = pick(times)
     record(key, best, times)
     return best
+
+
+def pick(times: dict, tie: float = 0.02) -> int:
+    """The lowest-numbered configuration within `tie` (relative) of the
+    fastest: configurations that time alike are chosen the same way on every
+    run, whatever the timing noise."""
+    t_min = min(times.values())
+    return min(i for i, t in times.items() if t <= t_min * (1.0 + tie))
 
 
 def tune_batched(As, Bs, r: int, basis, prec: str = "bf16", transA=False, transB=False, reps: int = 3,
@@ -148,6 +156,6 @@ def tune_batched(As, Bs, r: int, basis, prec: str = "bf16", transA=False, transB
         times[i] = _time_ms(lambda: pg.gemm_batched(As, Bs, r, basis, prec=prec, transA=transA, transB=transB,
                                                     outs=outs, tile_cfg=i, workspace=ws), reps, warmup=1)
         del ws
-    best = min(times, key=times.get)
+    best = pick(times)
     record(key, best, times)
     return best

@@ -34,6 +34,12 @@ def test_record_lookup_persist(tmp_cache):
     assert d[key]["cfg"] == 3 and d[key]["ms"]["3"] == 0.5
 
 
+def test_pick_breaks_ties_by_index():
+    assert autotune.pick({0: 2.0, 9: 1.00, 10: 0.99}) == 9          # within 2 %: lowest index
+    assert autotune.pick({0: 2.0, 9: 1.05, 10: 1.00}) == 10         # a clear winner
+    assert autotune.pick({3: 1.0}) == 3
+
+
 @pytest.mark.gpu
 def test_tune_gemm_and_batched_on_device(tmp_cache):
     torch = pytest.importorskip("torch")
