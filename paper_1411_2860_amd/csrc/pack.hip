@@ -9,17 +9,25 @@
 // A side: coef = C (A_c = A C_N, eq. (5), (15)).  B side: the source is B^T
 // (rows = columns of B) and coef = D^T, i.e. B_d = D_N B.
 //
-// One workgroup owns RB source rows (one row block of the packed operand) and
-// KB consecutive groups j (one k-block per projection), for every projection
-// l < r.  The source tile is staged through LDS in chunks of TC indices t,
-// laid out [row][group][t] with padded strides so that the 16-byte LDS reads
-// of a wavefront spread evenly over the banks.  Lane (row, g) accumulates the
-// E consecutive groups of its lane vector for RL projections at a time; the
-// coefficients are wave-uniform scalars, each used for 4 t x E groups.  Every
-// wave writes whole 64-lane tiles, so stores are fully coalesced.
+// One workgroup owns TRc source rows and KB consecutive groups j (one k-block
+// per projection), for every projection l < r.  The source tile is staged
+// through LDS in rounds of TC indices t, in one of three round layouts:
+//   0  [row][group][t] with padded strides, filled through registers
+//      (16-byte or element loads);
+//   1  swizzled and unpadded, filled by direct global-to-LDS loads (16 bytes
+//      per lane for aligned rows, else one value per lane);
+//   2  transposed ([group][t][row], rows padded), filled by single-value
+//      direct loads from a transposed source.
+// FP32-input tiles of 32 rows project on the FP32 matrix cores (16 x 16 x 4),
+// 16 projections per pass, and return the results to the store layout
+// through LDS; otherwise lane (row, g) accumulates the E consecutive groups
+// of its lane vector for RL projections at a time with vector FMAs, the
+// coefficients being wave-uniform scalars.  Every wave writes whole 64-lane
+// tiles, so stores are fully coalesced.
 //
-// Both operands of a GEMM can be packed by ONE launch (two jobs over one
-// grid), so the small A side overlaps with the large B side.
+// Both operands of a GEMM are packed by one launch (two jobs over one grid,
+// so the small A side overlaps with the large B side) when they use the same
+// round layout, else by one launch each.
 #include <vector>
 
 #include <algorithm>
