@@ -124,12 +124,12 @@ def tune_gemm(M: int, W: int, K: int, L: int, r: int, prec: str = "f32", reps: i
     return best
 
 
-def pick(times: dict, tie: float = 0.02) -> int:
-    """The lowest-numbered configuration within `tie` (relative) of the
-    fastest: configurations that time alike are chosen the same way on every
-    run, whatever the timing noise."""
+def pick(times: dict, tie: float = 0.03) -> int:
+    """The highest-numbered configuration (the table ends with the largest
+    tiles) within `tie` (relative) of the fastest: configurations that time
+    alike are chosen the same way on every run, whatever the timing noise."""
     t_min = min(times.values())
-    return min(i for i, t in times.items() if t <= t_min * (1.0 + tie))
+    return max(i for i, t in times.items() if t <= t_min * (1.0 + tie))
 
 
 def tune_batched(As, Bs, r: int, basis, prec: str = "bf16", transA=False, transB=False, reps: int = 3,

@@ -35,8 +35,8 @@ def test_record_lookup_persist(tmp_cache):
 
 
 def test_pick_breaks_ties_by_index():
-    assert autotune.pick({0: 2.0, 9: 1.00, 10: 0.99}) == 9          # within 2 %: lowest index
-    assert autotune.pick({0: 2.0, 9: 1.05, 10: 1.00}) == 10         # a clear winner
+    assert autotune.pick({0: 2.0, 9: 0.99, 10: 1.01}) == 10         # within 3 %: highest index
+    assert autotune.pick({0: 2.0, 9: 1.00, 10: 1.05}) == 9          # a clear winner
     assert autotune.pick({3: 1.0}) == 3
 
 
