@@ -85,6 +85,16 @@ def test_ragged(pg, W, N, L, kind):
         _check(pg, s, k, kind, L, r)
 
 
+@pytest.mark.parametrize("r", [7, 33])
+def test_half_kblock_phases(pg, r):
+    """12 kernel blocks per projection (N = 500, L = 64): every k-block of 8
+    contraction indices after the first spans two projections, and with odd
+    r the last one is half empty."""
+    s = inputs.ar2_signal(20000, seed=27)
+    k, _ = inputs.excerpt_kernel(s, 500, seed=28)
+    _check(pg, s, k, "dct2", 64, r)
+
+
 @pytest.mark.parametrize("r", [1, 3, 8])
 def test_convolution_mode(pg, r):
     s = inputs.ar2_signal(5000, seed=25)
