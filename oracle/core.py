@@ -30,7 +30,7 @@ __all__ = [
     "xcorr_proj_closed", "xcorr_proj_sliding", "xcorr_proj_block_rate", "xcorr_proj_block_rate_at", "xcorr_proj_circular",
     "block_moments", "block_moments_brute", "basis_klt", "pca2d",
     "rel_fro", "snr_db", "work_gemm_plain", "work_gemm_proj",
-    "work_conv_plain_time", "work_conv_proj_time",
+    "work_conv_plain_time", "work_conv_proj_time", "work_conv_plain_freq", "work_conv_proj_freq",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -584,3 +584,16 @@ def work_conv_plain_time(N: int) -> int:
 def work_conv_proj_time(N: int, l: int, L: int) -> int:
     """eq. (20): projection MACs plus the reduced time-domain CONVs."""
     return (l + 1) * (4 * N + 1) + 2 * (l + 1) * (-(-N // L)) ** 2
+
+
+def work_conv_plain_freq(N: int) -> float:
+    """eq. (19): approximate MACs of an FFT-based CONV of a kernel of N
+    samples on the minimum overlap-save block of 3N + 1 samples."""
+    return (45 * N + 15) * math.log2(3 * N + 1) + 3 * N + 1
+
+
+def work_conv_proj_freq(N: int, l: int, L: int) -> float:
+    """eq. (21): projection MACs plus l + 1 FFT-based CONVs of the
+    down-sampled signal and kernel (ceil(N / L) samples each)."""
+    n = -(-N // L)
+    return (l + 1) * (4 * N + 1) + (l + 1) * ((45 * n + 15) * math.log2(3 * n + 1) + 3 * n + 1)

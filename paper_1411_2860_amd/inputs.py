@@ -46,9 +46,14 @@ def gaussian_taps(sigma: float) -> np.ndarray:
 
 
 def _to_uint8_range(x: np.ndarray, axes) -> np.ndarray:
+    """Min-max scaling to [0, 255], rounded; a constant slice (one sample, or
+    equal samples) has no range to scale and becomes the mid value 128."""
     lo = x.min(axis=axes, keepdims=True)
     hi = x.max(axis=axes, keepdims=True)
-    return np.rint((x - lo) / (hi - lo) * 255.0)
+    span = hi - lo
+    flat = span == 0
+    scaled = (x - lo) / np.where(flat, 1.0, span) * 255.0
+    return np.rint(np.where(flat, 128.0, scaled))
 
 
 def smoothed_field(rows: int, cols: int, sigma: float = 4.0, seed: int = SEED_CFG1_A) -> np.ndarray:

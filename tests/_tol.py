@@ -51,12 +51,24 @@ def gemm_bound(prec, L, r, Gp, mag, safety=4.0):
 
 
 def assert_within(got, ref, bound, what=""):
+    """|got - ref| <= bound element by element.  Every value of `got` must be
+    finite (a NaN or an infinity never passes), and so must `ref`."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
+    bound = np.broadcast_to(np.asarray(bound, dtype=np.float64), got.shape)
+    if got.shape != ref.shape:
+        raise AssertionError(f"{what}: shape {got.shape} != reference shape {ref.shape}")
+    if not np.isfinite(ref).all():
+        raise AssertionError(f"{what}: the reference holds non-finite values")
+    nonfinite = ~np.isfinite(got)
+    if nonfinite.any():
+        i = np.unravel_index(np.argmax(nonfinite), got.shape)
+        raise AssertionError(f"{what}: {int(nonfinite.sum())} of {got.size} values not finite; first at {i}: "
+                             f"{got[i]!r}")
     err = np.abs(got - ref)
-    bad = err > bound
+    bad = ~(err <= bound)
     if np.any(bad):
-        i = np.unravel_index(np.argmax(err - bound), err.shape)
+        i = np.unravel_index(np.argmax(np.where(bad, err - bound, -np.inf)), err.shape)
         raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside bound; worst at {i}: "
                              f"got {got[i]!r} ref {ref[i]!r} err {err[i]:.3e} bound {bound[i]:.3e}")
 

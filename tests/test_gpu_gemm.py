@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_1411_2860_amd import inputs
-from tests import _tol
+from tests import _ref, _tol
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -40,7 +40,7 @@ def _run(pg, A, B, basis, r, prec, transA=False, transB=False):
 
 def _check(pg, A, B, kind, L, r, prec, transA=False, transB=False, Cc=None):
     basis = pg.Basis(kind, L, Cc)
-    C, D = basis.matrices()          # the library's own FP64 basis (any column scaling)
+    C, D = _ref.oracle_basis(kind, L, Cc)
     got = _run(pg, A, B, basis, r, prec, transA, transB)
     ref = oracle.gemm_proj(A, B, C, D, r)
     if prec in ("f32", "f64"):
@@ -157,7 +157,7 @@ def test_beta_accumulates(pg):
     B = rng.standard_normal((64, 50)).astype(np.float32)
     R0 = rng.standard_normal((40, 50)).astype(np.float32)
     basis = pg.Basis("dct2", 16)
-    C, D = basis.matrices()
+    C, D = _ref.oracle_basis("dct2", 16)
     out = _dev(R0, torch.float32)
     pg.gemm(_dev(A, torch.float32), _dev(B, torch.float32), 4, basis, beta=0.5, out=out)
     torch.cuda.synchronize()
@@ -198,7 +198,7 @@ def test_full_size_sampled(pg, full_images, r):
     is below 1e-5."""
     A, Bt = full_images
     basis = pg.Basis("dct2", 64)
-    C, D = basis.matrices()
+    C, D = _ref.oracle_basis("dct2", 64)
     R = pg.gemm(_dev(A, torch.float32), _dev(Bt, torch.float32), r, basis, transB=True)
     torch.cuda.synchronize()
     rng = np.random.default_rng(r)
@@ -227,7 +227,7 @@ def test_skinny_output_split_contraction(pg, prec, r, L, K, beta):
     B = rng.standard_normal((K, W))
     R0 = rng.standard_normal((M, W))
     basis = pg.Basis("dct2", L)
-    C, D = basis.matrices()
+    C, D = _ref.oracle_basis("dct2", L)
     dt = torch.float64 if prec == "f64" else torch.float32
     Ad, Bd = torch.from_numpy(A).to(dt).cuda(), torch.from_numpy(B).to(dt).cuda()
     R = torch.from_numpy(R0).to(dt).cuda()

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_1411_2860_amd import inputs
-from tests import _tol
+from tests import _ref, _tol
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -45,27 +45,40 @@ def test_block_moments(pg, rows, K, L, pad):
 
 @pytest.mark.parametrize("r", [1, 2, 4, 8, 16])
 def test_projected_gemm_with_trained_basis(pg, r):
-    """Train on database-like image rows, then the projected GEMM with that
-    basis against the oracle (same C, D) within the FP32 bound; and on the
-    training rows themselves the KLT never loses to the DCT-II."""
+    """Train on database-like image rows.  The library's eigenbasis (device
+    moments, host eigensolver) spans the same leading subspace as the
+    oracle's (its projector is what the method uses, and it is unique where
+    the eigenvalues are separated); on the training rows it never loses to
+    the DCT-II and its residual is the tail eigenvalue sum (Eckart-Young).
+    Then the projected GEMM with the oracle's eigenbasis, given to the
+    library as a custom matrix, against the oracle within the FP32 bound."""
     L = 16
     train = inputs.image_rows(256, seed_base=inputs.SEED_IMG_BASE, first=5000).astype(np.float32)
+    T = train.astype(np.float64)
     M = pg.block_moments(torch.from_numpy(train).cuda(), L)
     basis, eig = pg.klt_basis(M)
-    C, D = basis.matrices()
-    A = inputs.image_rows(64, seed_base=inputs.SEED_IMG_BASE).astype(np.float64)
-    B = inputs.gaussian_matrix(4096, 96, seed=77)
-    R = pg.gemm(torch.from_numpy(A).float().cuda(), torch.from_numpy(B).float().cuda(), r, basis, prec="f32")
-    torch.cuda.synchronize()
-    ref = oracle.gemm_proj(A, B, C, D, r)
-    Gp = -(-(4096 // L) // 8) * 8
-    bound = _tol.gemm_bound("f32", L, r, Gp, _tol.magnitude(A, B, C, D, r))
-    _tol.assert_within(R.double().cpu().numpy(), ref, bound, f"klt r={r}")
-    T = train.astype(np.float64)
-    Q = oracle.blockdiag(oracle.q_matrix(C, D, r), T.shape[1] // L)
+    Cl, Dl = basis.matrices()                      # the library's output, under test
+    Co, Do, wo = oracle.basis_klt(oracle.block_moments(T, L))
+    np.testing.assert_allclose(eig, wo, rtol=1e-9, atol=1e-12 * wo[0])
+    gap = wo[r - 1] - (wo[r] if r < L else 0.0)
+    # the projectors differ by about the eigensolver error over the gap
+    dq = np.linalg.norm(oracle.q_matrix(Cl, Dl, r) - oracle.q_matrix(Co, Do, r))
+    assert dq <= 1e-9 * wo[0] / max(gap, 1e-300) + 1e-12
+    Q = oracle.blockdiag(oracle.q_matrix(Cl, Dl, r), T.shape[1] // L)
     Cd, Dd = oracle.basis("dct2", L)
     Qd = oracle.blockdiag(oracle.q_matrix(Cd, Dd, r), T.shape[1] // L)
     res_klt = np.linalg.norm(T - T @ Q) ** 2
     res_dct = np.linalg.norm(T - T @ Qd) ** 2
     assert res_klt <= res_dct * (1 + 1e-9) + 1e-12 * np.linalg.norm(T) ** 2
-    np.testing.assert_allclose(res_klt, eig[r:].sum(), rtol=1e-6, atol=1e-9 * eig.sum())
+    np.testing.assert_allclose(res_klt, wo[r:].sum(), rtol=1e-6, atol=1e-9 * wo.sum())
+
+    kb = pg.Basis("custom", L, Co)
+    A = inputs.image_rows(64, seed_base=inputs.SEED_IMG_BASE).astype(np.float64)
+    B = inputs.gaussian_matrix(4096, 96, seed=77)
+    R = pg.gemm(torch.from_numpy(A).float().cuda(), torch.from_numpy(B).float().cuda(), r, kb, prec="f32")
+    torch.cuda.synchronize()
+    C, D = _ref.oracle_basis("custom", L, Co)
+    ref = oracle.gemm_proj(A, B, C, D, r)
+    Gp = -(-(4096 // L) // 8) * 8
+    bound = _tol.gemm_bound("f32", L, r, Gp, _tol.magnitude(A, B, C, D, r))
+    _tol.assert_within(R.double().cpu().numpy(), ref, bound, f"klt r={r}")

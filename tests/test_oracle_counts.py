@@ -48,3 +48,24 @@ def test_snr_definition():
     assert abs(oracle.snr_db(ref, approx) - 10 * math.log10(2.0 / 0.01)) < 1e-12
     assert oracle.snr_db(ref, ref) == math.inf
     assert abs(oracle.rel_fro(approx, ref) - 0.1 / math.sqrt(2.0)) < 1e-15
+
+
+def test_conv_time_counts_match_hand_worked_values():
+    # eq. (18) and (20) against values worked by hand from the printed
+    # formulas (a dropped term, a missing ceil or a wrong factor fails)
+    for c in _golden()["conv_work_counts"]["cases"]:
+        assert oracle.work_conv_plain_time(c["N"]) == c["plain_time"]
+        assert oracle.work_conv_proj_time(c["N"], c["l"], c["L"]) == c["proj_time"]
+
+
+def test_conv_freq_counts_match_hand_worked_values():
+    # eq. (19) and (21) at N = 341 (3N + 1 = 1024, an exact power of two)
+    g = _golden()["conv_work_counts_freq"]
+    assert oracle.work_conv_plain_freq(g["N"]) == g["plain_freq"]
+    want = (g["proj_freq_projection"] + g["proj_freq_fft_coef"] * math.log2(g["proj_freq_log2_arg"])
+            + g["proj_freq_tail"])
+    assert abs(oracle.work_conv_proj_freq(g["N"], g["l"], g["L"]) - want) < 1e-9 * want
+    # the frequency-domain model favours projections more as N grows
+    r1 = oracle.work_conv_proj_freq(1 << 14, 0, 256) / oracle.work_conv_plain_freq(1 << 14)
+    r2 = oracle.work_conv_proj_freq(1 << 20, 0, 256) / oracle.work_conv_plain_freq(1 << 20)
+    assert r2 < r1 < 1.0

@@ -57,6 +57,66 @@ def test_haar_columns_orthogonal_and_l2_equals_dct(L):
         np.testing.assert_allclose(H[:, 1] * C[0, 1], C[:, 1], atol=1e-15)
 
 
+# Haar bases written out by hand in the order of the reading of Sec. IV-A /
+# V-B (scaling function, then wavelets from the coarsest scale to the finest,
+# shifts ascending within a scale), unnormalised +1 / -1 / 0.
+HAAR4_BY_HAND = np.array([
+    [1, 1, 1, 0],
+    [1, 1, -1, 0],
+    [1, -1, 0, 1],
+    [1, -1, 0, -1],
+], dtype=float)
+HAAR8_BY_HAND = np.array([
+    [1, 1, 1, 0, 1, 0, 0, 0],
+    [1, 1, 1, 0, -1, 0, 0, 0],
+    [1, 1, -1, 0, 0, 1, 0, 0],
+    [1, 1, -1, 0, 0, -1, 0, 0],
+    [1, -1, 0, 1, 0, 0, 1, 0],
+    [1, -1, 0, 1, 0, 0, -1, 0],
+    [1, -1, 0, -1, 0, 0, 0, 1],
+    [1, -1, 0, -1, 0, 0, 0, -1],
+], dtype=float)
+
+
+@pytest.mark.parametrize("L,H", [(4, HAAR4_BY_HAND), (8, HAAR8_BY_HAND)])
+def test_haar_columns_match_hand_written(L, H):
+    # column by column: swapping two wavelets or reversing the scale order fails
+    np.testing.assert_array_equal(oracle.basis_haar(L), H)
+
+
+def _segment_average(x, bounds):
+    """Replace x on each [lo, hi) of `bounds` by its mean there."""
+    y = np.empty_like(x)
+    for lo, hi in bounds:
+        y[..., lo:hi] = x[..., lo:hi].mean(axis=-1, keepdims=True)
+    return y
+
+
+@pytest.mark.parametrize("L", [2, 4, 8, 16, 32])
+def test_haar_projection_is_multiresolution_average(L):
+    # Multiresolution property of the Haar basis: the scaling function and the
+    # wavelets of the s coarsest scales span the functions that are constant
+    # on 2^s equal segments, and adding the first j wavelets of the next scale
+    # splits the first j of those segments in two.  So the block reconstruction
+    # from the first r = 2^s + j columns is a segment average, computed here
+    # without any basis matrix.
+    C, D = oracle.basis("haar", L)
+    x = _rand((3, L), 11)
+    for r in range(1, L + 1):
+        s = int(np.floor(np.log2(r)))
+        j = r - (1 << s)
+        seg = L >> s                        # segment length at scale s
+        bounds = []
+        for p in range(1 << s):
+            lo = p * seg
+            if p < j:                       # split by the next scale's wavelet p
+                bounds += [(lo, lo + seg // 2), (lo + seg // 2, lo + seg)]
+            else:
+                bounds.append((lo, lo + seg))
+        Q = C[:, :r] @ D[:r, :]
+        np.testing.assert_allclose(x @ Q, _segment_average(x, bounds), atol=1e-12)
+
+
 def test_haar_rejects_non_power_of_two():
     with pytest.raises(RuntimeError):
         oracle.basis_haar(6)
