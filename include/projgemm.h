@@ -47,7 +47,8 @@ typedef enum {
     PJ_ERR_UNSUPPORTED = -3,  /* valid request the library does not implement   */
     PJ_ERR_WORKSPACE = -4,    /* workspace missing or smaller than the query    */
     PJ_ERR_SINGULAR = -5,     /* custom projection matrix is not invertible     */
-    PJ_ERR_HIP = -6           /* a HIP runtime call or kernel launch failed     */
+    PJ_ERR_HIP = -6,          /* a HIP runtime call or kernel launch failed     */
+    PJ_ERR_SCRATCH = -7       /* proj_gemm_noalloc: request exceeds its scratch */
 } pj_status;
 
 typedef enum {
@@ -134,6 +135,29 @@ int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K,
               const void* A, int64_t lda, const void* B, int64_t ldb,
               float beta, void* R, int64_t ldr, int prec,
               void* ws, size_t ws_bytes, void* stream);
+
+/* ---- allocation-free variant ------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): proj_gemm
+ * with no workspace argument.  Its scratch (the two packed operands and, for
+ * skinny outputs, the contraction-range partials) lives in one fixed array of
+ * PJ_NOALLOC_SCRATCH_BYTES in device memory per GPU, reserved when the
+ * library is loaded and held until the process ends.  The call allocates
+ * nothing and calls no allocating routine.
+ *   - Same arguments, results, layouts and errors as proj_gemm, plus
+ *     PJ_ERR_SCRATCH (returned before any device work) when
+ *     pj_gemm_workspace_bytes(M, W, K, L, r, prec) > PJ_NOALLOC_SCRATCH_BYTES.
+ *   - Every call on one GPU shares that GPU's array and leaves its contents
+ *     behind; nothing in it needs to start at zero.  Calls that overlap on
+ *     one GPU (e.g. on two streams without ordering between them) race on the
+ *     array and must not be issued.
+ *   - The first call on a device looks the array's address up (a runtime
+ *     query, no allocation) with that device current. */
+#define PJ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+int proj_gemm_noalloc(pj_basis b, int r, char transA, char transB, int M, int W, int K,
+                      const void* A, int64_t lda, const void* B, int64_t ldb,
+                      float beta, void* R, int64_t ldr, int prec, void* stream);
 
 /* ---- the same path in separate steps (a static B packed once, r sweeps) --
  * A packed operand holds `rows` rows of a matrix projected onto the first

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -281,6 +282,7 @@ const char* pj_status_str(int s)
     case PJ_ERR_WORKSPACE: return "workspace missing or too small";
     case PJ_ERR_SINGULAR: return "projection matrix is singular";
     case PJ_ERR_HIP: return "HIP runtime or launch failure";
+    case PJ_ERR_SCRATCH: return "request needs more than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
@@ -459,9 +461,9 @@ static int gemm_packed_impl(int r, int M, int W, int K, int L, int prec, const v
     return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
 }
 
-int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
-              const void* B, int64_t ldb, float beta, void* R, int64_t ldr, int prec, void* ws, size_t ws_bytes,
-              void* stream)
+// Argument checks of proj_gemm (host only, before any device work).
+static int check_proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A,
+                           int64_t lda, const void* B, int64_t ldb, const void* R, int64_t ldr, int prec)
 {
     if (!b || !A || !B || !R) return PJ_ERR_ARG;
     if (!valid_prec(prec)) return PJ_ERR_ARG;
@@ -473,9 +475,15 @@ int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, 
     if (ldr < W) return PJ_ERR_SHAPE;
     if ((prec == PJ_FP8 || prec == PJ_FP8X2) && r > 8) return PJ_ERR_UNSUPPORTED;
     if (!implemented_prec(prec)) return PJ_ERR_UNSUPPORTED;
-    const size_t need = pj_gemm_workspace_bytes(M, W, K, b->L, r, prec);
-    if (!ws || ws_bytes < need) return PJ_ERR_WORKSPACE;
-    if (!b->on_device) return PJ_ERR_HIP;
+    return PJ_OK;
+}
+
+// The device work of proj_gemm on a checked request and a workspace of at
+// least pj_gemm_workspace_bytes: pack both sides, then contract.
+static int run_proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A,
+                         int64_t lda, const void* B, int64_t ldb, float beta, void* R, int64_t ldr, int prec,
+                         void* ws, void* stream)
+{
     char* wa = (char*)ws;
     char* wb = wa + align256(pj_packed_bytes(M, K, b->L, r, prec));
     char* wp = wb + align256(pj_packed_bytes(W, K, b->L, r, prec));
@@ -490,6 +498,75 @@ int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, 
     return gemm_packed_impl(r, M, W, K, b->L, prec, wa, r, pj_packed_bytes(M, K, b->L, r, prec), wb, r,
                             pj_packed_bytes(W, K, b->L, r, prec), beta, R, ldr, -1, ns, ns > 1 ? wp : nullptr,
                             stream);
+}
+
+int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
+              const void* B, int64_t ldb, float beta, void* R, int64_t ldr, int prec, void* ws, size_t ws_bytes,
+              void* stream)
+{
+    int rc = check_proj_gemm(b, r, transA, transB, M, W, K, A, lda, B, ldb, R, ldr, prec);
+    if (rc != PJ_OK) return rc;
+    const size_t need = pj_gemm_workspace_bytes(M, W, K, b->L, r, prec);
+    if (!ws || ws_bytes < need) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    return run_proj_gemm(b, r, transA, transB, M, W, K, A, lda, B, ldb, beta, R, ldr, prec, ws, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free variant
+//
+// proj_gemm_noalloc runs proj_gemm's kernels on a fixed scratch array in
+// device memory instead of a caller workspace, for callers that cannot
+// allocate.  Each device holds its own copy of the array at its own address;
+// in host code `scratch` is only a stand-in for that address, so the address
+// is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only the looked-up pointer is ever handed to kernels.
+namespace {
+
+static_assert(PJ_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size must keep 256-byte alignment");
+static __device__ __align__(256) unsigned char scratch[PJ_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+int current_scratch(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) {
+        (void)hipGetLastError();
+        return PJ_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return PJ_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int proj_gemm_noalloc(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
+                      const void* B, int64_t ldb, float beta, void* R, int64_t ldr, int prec, void* stream)
+{
+    int rc = check_proj_gemm(b, r, transA, transB, M, W, K, A, lda, B, ldb, R, ldr, prec);
+    if (rc != PJ_OK) return rc;
+    if (pj_gemm_workspace_bytes(M, W, K, b->L, r, prec) > PJ_NOALLOC_SCRATCH_BYTES) return PJ_ERR_SCRATCH;
+    if (!b->on_device) return PJ_ERR_HIP;
+    void* ws = nullptr;
+    rc = current_scratch(&ws);
+    if (rc != PJ_OK) return rc;
+    return run_proj_gemm(b, r, transA, transB, M, W, K, A, lda, B, ldb, beta, R, ldr, prec, ws, stream);
 }
 
 // ---------------------------------------------------------------- batched

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "ProjGemmError", "lib", "lib_path", "Basis", "PREC", "BASIS",
-    "gemm", "pack_a", "pack_b", "pack_ab", "tile_configs", "gemm_packed", "packed_bytes", "gemm_workspace_bytes",
+    "gemm", "gemm_noalloc", "pack_a", "pack_b", "pack_ab", "tile_configs", "gemm_packed", "packed_bytes", "gemm_workspace_bytes",
     "conv1d", "conv1d_workspace_bytes", "gemm_backward", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
     "status_str",
 ]
@@ -28,7 +28,8 @@ _lib = None
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3, "f16": 4, "f16x3": 5, "fp8": 6, "fp8x2": 7}
 BASIS = {"dct2": 0, "haar": 1, "identity": 2, "custom": 3}
 STATUS = {0: "PJ_OK", -1: "PJ_ERR_ARG", -2: "PJ_ERR_SHAPE", -3: "PJ_ERR_UNSUPPORTED",
-          -4: "PJ_ERR_WORKSPACE", -5: "PJ_ERR_SINGULAR", -6: "PJ_ERR_HIP"}
+          -4: "PJ_ERR_WORKSPACE", -5: "PJ_ERR_SINGULAR", -6: "PJ_ERR_HIP", -7: "PJ_ERR_SCRATCH"}
+NOALLOC_SCRATCH_BYTES = 64 << 20      # PJ_NOALLOC_SCRATCH_BYTES of the header
 
 
 class ProjGemmError(RuntimeError):
@@ -58,6 +59,7 @@ _SIGNATURES = {
     "pj_gemm_workspace_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
     "pj_packed_bytes": (_sz, [_i, _i, _i, _i, _i]),
     "proj_gemm": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _f, _vp, _i64, _i, _vp, _sz, _vp]),
+    "proj_gemm_noalloc": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _f, _vp, _i64, _i, _vp]),
     "pj_pack_a": (_i, [_vp, _i, _ch, _i, _i, _vp, _i64, _i, _vp, _sz, _vp]),
     "pj_pack_b": (_i, [_vp, _i, _ch, _i, _i, _vp, _i64, _i, _vp, _sz, _vp]),
     "pj_gemm_packed": (_i, [_i, _i, _i, _i, _i, _i, _vp, _i, _sz, _vp, _i, _sz, _f, _vp, _i64, _i, _vp]),
@@ -256,6 +258,31 @@ def gemm(A, B, r: int, basis: Basis, prec="f32", transA=False, transB=False, bet
                            _ptr(A), A.stride(0), _ptr(B), B.stride(0), float(beta), _ptr(out), out.stride(0), p,
                            _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)),
            "proj_gemm")
+    return out
+
+
+def gemm_noalloc(A, B, r: int, basis: Basis, out, prec="f32", transA=False, transB=False, beta=0.0, stream=None):
+    """proj_gemm_noalloc: the same product as gemm() on the library's fixed
+    per-device scratch, with no workspace; `out` (M x W) is the caller's."""
+    p = _prec(prec)
+    if transA:
+        K, M = A.shape
+    else:
+        M, K = A.shape
+    if transB:
+        W, K2 = B.shape
+    else:
+        K2, W = B.shape
+    if K2 != K:
+        raise ValueError(f"contraction mismatch {K} vs {K2}")
+    if A.stride(1) != 1 or B.stride(1) != 1 or out.stride(1) != 1:
+        raise ValueError("A, B and out need unit stride along their last dimension")
+    if tuple(out.shape) != (M, W):
+        raise ValueError(f"out must be {M} x {W}")
+    _check(lib().proj_gemm_noalloc(basis.handle, r, b"T" if transA else b"N", b"T" if transB else b"N", M, W, K,
+                                   _ptr(A), A.stride(0), _ptr(B), B.stride(0), float(beta), _ptr(out),
+                                   out.stride(0), p, _stream(stream)),
+           "proj_gemm_noalloc")
     return out
 
 

@@ -15,7 +15,7 @@ from paper_1411_2860_amd import projgemm as pg
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "projgemm.h")
 
-OK, ARG, SHAPE, UNSUP, WS, SING, HIP = 0, -1, -2, -3, -4, -5, -6
+OK, ARG, SHAPE, UNSUP, WS, SING, HIP, SCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
 
 
@@ -55,7 +55,7 @@ def test_tile_configs(lib):
 
 
 def test_status_strings(lib):
-    for c in (OK, ARG, SHAPE, UNSUP, WS, SING, HIP):
+    for c in (OK, ARG, SHAPE, UNSUP, WS, SING, HIP, SCRATCH):
         assert pg.status_str(c) and pg.status_str(c) != "unknown status"
 
 
@@ -152,6 +152,27 @@ def test_valid_call_without_device_reports_hip(lib, basis16):
     if torch.cuda.is_available():
         pytest.skip("a device is present")
     assert _gemm(lib, basis16) == HIP
+
+
+def test_noalloc_validation_and_scratch_limit(lib, basis16):
+    """proj_gemm_noalloc rejects what proj_gemm rejects, and a request whose
+    workspace exceeds the fixed scratch, before any device work."""
+    b = basis16
+
+    def call(M=32, W=32, K=64, r=4, prec=1, A=FAKE, lda=None):
+        return lib.proj_gemm_noalloc(b.handle, r, b"N", b"N", M, W, K, A, lda or K, FAKE, W, 0.0, FAKE, W,
+                                     prec, None)
+    assert call(A=None) == ARG
+    assert call(r=0) == ARG
+    assert call(M=0) == SHAPE
+    assert call(lda=3) == SHAPE
+    assert call(prec=6, r=9) == UNSUP
+    M, W, K, r = 8192, 8192, 4096, 16
+    assert pg.gemm_workspace_bytes(M, W, K, 16, r) > pg.NOALLOC_SCRATCH_BYTES
+    assert call(M=M, W=W, K=K, r=r) == SCRATCH
+    assert pg.NOALLOC_SCRATCH_BYTES == 64 << 20
+    text = open(HEADER).read()
+    assert "#define PJ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in text
 
 
 def test_pack_and_packed_gemm_validation(lib, basis16):
