@@ -25,6 +25,7 @@ struct pj_basis_s {
     int device = -1;
     float* Cf = nullptr;             // C[t][l]           (A side coefficients)
     float* DTf = nullptr;            // D^T[t][l] = D[l][t] (B side coefficients)
+    float* CTf = nullptr;            // C^T[l][t] = C[t][l] (synthesis with C, coalesced over t)
     double* Cd = nullptr;
     double* DTd = nullptr;
     float* I4f = nullptr;            // 4 x 4 identity: packs an operand unprojected
@@ -159,6 +160,7 @@ void free_device(pj_basis b)
     (void)hipSetDevice(b->device);
     (void)hipFree(b->Cf);
     (void)hipFree(b->DTf);
+    (void)hipFree(b->CTf);
     (void)hipFree(b->Cd);
     (void)hipFree(b->DTd);
     (void)hipFree(b->I4f);
@@ -183,16 +185,19 @@ bool upload(pj_basis b)
     if (hipGetDevice(&b->device) != hipSuccess) return false;
     const int L = b->L;
     const size_t n = (size_t)L * L;
-    std::vector<float> cf(n), dtf(n);
+    std::vector<float> cf(n), dtf(n), ctf(n);
     std::vector<double> dtd(n);
     for (int t = 0; t < L; ++t)
         for (int l = 0; l < L; ++l) {
             cf[(size_t)t * L + l] = (float)b->C[(size_t)t * L + l];
+            ctf[(size_t)l * L + t] = (float)b->C[(size_t)t * L + l];
             dtd[(size_t)t * L + l] = b->D[(size_t)l * L + t];
             dtf[(size_t)t * L + l] = (float)b->D[(size_t)l * L + t];
         }
     bool ok = hipMalloc((void**)&b->Cf, n * sizeof(float)) == hipSuccess &&
               hipMalloc((void**)&b->DTf, n * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&b->CTf, n * sizeof(float)) == hipSuccess &&
+              hipMemcpy(b->CTf, ctf.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc((void**)&b->Cd, n * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&b->DTd, n * sizeof(double)) == hipSuccess &&
               hipMemcpy(b->Cf, cf.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
@@ -845,7 +850,7 @@ int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, c
     a.s = s; a.W = W; a.k = k; a.N = N;
     a.reverse = (mode == PJ_CONV);
     a.L = b->L; a.r = r;
-    a.C = b->Cf; a.DT = b->DTf;
+    a.C = b->Cf; a.DT = b->DTf; a.CT = b->CTf;
     a.y = y; a.ws = ws;
     return launch_conv(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
 }
@@ -876,7 +881,7 @@ int proj_conv1d_circular(pj_basis b, int r, int mode, int64_t W, const float* s,
     a.s = s; a.W = Wv; a.k = k; a.N = N;
     a.reverse = (mode == PJ_CONV);
     a.L = b->L; a.r = r;
-    a.C = b->Cf; a.DT = b->DTf;
+    a.C = b->Cf; a.DT = b->DTf; a.CT = b->CTf;
     a.y = y; a.ws = ws;
     a.period = W;
     return launch_conv(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
@@ -902,7 +907,8 @@ int proj_conv1d_rate(pj_basis b, int r, int mode, int rate, int64_t W, const flo
     if (W < 1 || N < 1 || N > W) return PJ_ERR_SHAPE;
     if (prec != PJ_F32) return PJ_ERR_UNSUPPORTED;
     const ConvBlockGeom g = conv_block_geom(W, N, b->L, r);
-    if (cdiv(g.nbp, 128) > 0x7fffffff || cdiv((int64_t)r * g.ncb, 256) > 0x7fffffff || cdiv(g.nout, 256) > 0x7fffffff)
+    if (cdiv(g.nbp, 128) > 0x7fffffff || cdiv((int64_t)g.nch * g.ntp, 256) > 0x7fffffff ||
+        cdiv(g.nout, 256) > 0x7fffffff || g.ntp > 0x7fffffff)
         return PJ_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < (size_t)g.total) return PJ_ERR_WORKSPACE;
     if (!b->on_device) return PJ_ERR_HIP;
@@ -910,7 +916,7 @@ int proj_conv1d_rate(pj_basis b, int r, int mode, int rate, int64_t W, const flo
     a.s = s; a.W = W; a.k = k; a.N = N;
     a.reverse = (mode == PJ_CONV);
     a.L = b->L; a.r = r;
-    a.C = b->Cf; a.DT = b->DTf;
+    a.C = b->Cf; a.DT = b->DTf; a.CT = b->CTf;
     a.y = y; a.ws = ws;
     return launch_conv_block(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
 }

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(64 * NW) void sig_project_kernel(
     const float* __restrict__ s, int64_t W, int L, int r, const float* __restrict__ C,
     float* __restrict__ sc, int64_t nbp)
 {
-    constexpr int PD = 4;                          // chunks in flight per lane
+    constexpr int PD = 8;                          // chunks in flight per lane
     __shared__ float Cs[kMaxConvL * 32];          // [t][l - l0]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -364,53 +364,9 @@ __global__ __launch_bounds__(256) void wrap_kernel(float* __restrict__ sc, int64
     sc[l * nbp + i] = sc[l * nbp + i % nb0];
 }
 
-// ---- short blocks (L <= kSmallL): vector-ALU path ----------------------------
-// With a handful of phases a 32-phase matrix-core tile would be mostly
-// padding; the phases are then kept in a plain layout
-//     kd[b][l][c] = kd_l[cL - b] = sum_u D[l, u] k'(cL - b + u)
-// and each output is one thread's dot products over the projections.
+// Blocks of at most kSmallL samples use the vector-ALU path of corr.hip (a
+// 32-phase matrix-core tile would be mostly padding there).
 constexpr int kSmallL = 8;
-
-__global__ __launch_bounds__(256) void kphase_plain_kernel(const float* __restrict__ k, int64_t N, int reverse, int L,
-                                                           int r, int64_t nc, const float* __restrict__ DT,
-                                                           float* __restrict__ kd)
-{
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;     // (b * r + l) * nc + c
-    if (idx >= (int64_t)L * r * nc) return;
-    const int64_t c = idx % nc;
-    const int l = (int)((idx / nc) % r);
-    const int b = (int)(idx / (nc * r));
-    float acc = 0.0f;
-    for (int u = 0; u < L; ++u) {
-        const int64_t n = c * L - b + u;
-        float kv = 0.0f;
-        if (n >= 0 && n < N) kv = reverse ? k[N - 1 - n] : k[n];
-        acc += DT[(int64_t)u * L + l] * kv;
-    }
-    kd[idx] = acc;
-}
-
-// y[aL + b] = sum_l sum_{c < nc} sc_l[a + c] kd[b][l][c], highest projection
-// first with one partial sum per projection.
-__global__ __launch_bounds__(256) void xcorr_small_kernel(const float* __restrict__ sc, int64_t nbp,
-                                                          const float* __restrict__ kd, int64_t nc, int L, int r,
-                                                          int64_t nout, float* __restrict__ y)
-{
-    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (m >= nout) return;
-    const int64_t a = m / L;
-    const int b = (int)(m - a * L);
-    float tot = 0.0f;
-    for (int l = r - 1; l >= 0; --l) {
-        const float* sp = sc + (int64_t)l * nbp + a;
-        const float* kp = kd + ((int64_t)b * r + l) * nc;
-        float part = 0.0f;
-#pragma unroll 8
-        for (int64_t c = 0; c < nc; ++c) part += sp[c] * kp[c];
-        tot += part;
-    }
-    y[m] = tot;
-}
 
 // Sum of the split partials, highest projection range first.
 __global__ __launch_bounds__(256) void split_sum_kernel(const float* __restrict__ part, int nsplit, int64_t nout,
@@ -420,60 +376,6 @@ __global__ __launch_bounds__(256) void split_sum_kernel(const float* __restrict_
     if (m >= nout) return;
     float v = part[(int64_t)(nsplit - 1) * nout + m];
     for (int s = nsplit - 2; s >= 0; --s) v += part[(int64_t)s * nout + m];
-    y[m] = v;
-}
-
-// ---- block rate: outputs at m = aL only, the others interpolated -------------
-// kd0[l][c] = sum_u D[l, u] k'(cL + u): the aligned kernel blocks projected
-// with the rows of D (phase b = 0 of step 2).
-__global__ __launch_bounds__(256) void kblock_kernel(const float* __restrict__ k, int64_t N, int reverse, int L, int r,
-                                                     int64_t ncb, const float* __restrict__ DT, float* __restrict__ kd0)
-{
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)r * ncb) return;
-    const int l = (int)(idx / ncb);
-    const int64_t c = idx - (int64_t)l * ncb;
-    float acc = 0.0f;
-#pragma unroll 8
-    for (int u = 0; u < L; ++u) {
-        const int64_t n = c * L + u;
-        const float kv = n < N ? (reverse ? k[N - 1 - n] : k[n]) : 0.0f;
-        acc += DT[(int64_t)u * L + l] * kv;
-    }
-    kd0[idx] = acc;
-}
-
-// yd[a] = sum_l sum_{c < ncb} sc_l[a + c] kd0[l][c]: the b = 0 column of the
-// reduced cross-correlation, one thread per computed output, highest
-// projection first with one partial sum per projection.
-__global__ __launch_bounds__(256) void xcorr_block_kernel(const float* __restrict__ sc, int64_t nbp,
-                                                          const float* __restrict__ kd0, int64_t ncb, int r, int64_t nd,
-                                                          float* __restrict__ yd)
-{
-    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (a >= nd) return;
-    float tot = 0.0f;
-    for (int l = r - 1; l >= 0; --l) {
-        const float* sp = sc + (int64_t)l * nbp + a;
-        const float* kp = kd0 + (int64_t)l * ncb;
-        float part = 0.0f;
-#pragma unroll 8
-        for (int64_t c = 0; c < ncb; ++c) part += sp[c] * kp[c];
-        tot += part;
-    }
-    yd[a] = tot;
-}
-
-// y[aL + f] = yd[a] + (f / L)(yd[a + 1] - yd[a]) while a + 1 < nd, else yd[a].
-__global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ yd, int64_t nd, int L, int64_t nout,
-                                                     float* __restrict__ y)
-{
-    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (m >= nout) return;
-    const int64_t a = m / L;
-    const int f = (int)(m - a * L);
-    float v = yd[a];
-    if (f != 0 && a + 1 < nd) v += ((float)f / (float)L) * (yd[a + 1] - v);
     y[m] = v;
 }
 
@@ -510,8 +412,13 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
     int64_t ns = std::max<int64_t>(1, std::max(fill, more));
     ns = std::min<int64_t>(ns, r);
     g.nsplit = g.small ? 1 : (int)ns;
+    if (g.small) {       // everything happens inside the workgroups (corr.hip)
+        g.sc_bytes = g.k_bytes = g.part_bytes = 0;
+        g.total = 256;
+        return g;
+    }
     g.sc_bytes = rup((int64_t)r * g.nbp * 4, 256);
-    g.k_bytes = g.small ? rup((int64_t)L * r * g.nc * 4, 256) : g.k_nrb * g.k_nkb * 1024;
+    g.k_bytes = g.k_nrb * g.k_nkb * 1024;
     g.part_bytes = g.nsplit > 1 ? rup((int64_t)g.nsplit * g.nout * 4, 256) : 0;
     g.total = g.sc_bytes + g.k_bytes + g.part_bytes;
     return g;
@@ -533,6 +440,15 @@ static int launch_sig_project(const ConvArgs& a, float* sc, int64_t nbp, hipStre
 int launch_conv(const ConvArgs& a, hipStream_t st)
 {
     const ConvGeom g = conv_geom(a.W, a.N, a.L, a.r);
+    if (g.small) {
+        CorrSmallArgs c;
+        c.s = a.s; c.W = a.W; c.period = a.period;
+        c.k = a.k; c.N = a.N; c.reverse = a.reverse;
+        c.L = a.L; c.r = a.r; c.C = a.C; c.DT = a.DT;
+        c.nrows = g.rows; c.ntap = g.nc; c.nout = g.nout;
+        c.y = a.y; c.block = 0;
+        return launch_corr_small(c, st);
+    }
     float* sc = (float*)a.ws;
     char* kp = (char*)a.ws + g.sc_bytes;
     // step 1
@@ -549,16 +465,6 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
         }
     } else if (launch_sig_project(a, sc, g.nbp, st) != 0) {
         return -1;
-    }
-    if (g.small) {
-        float* kd = (float*)kp;
-        const int64_t nk = (int64_t)a.L * a.r * g.nc;
-        hipLaunchKernelGGL(kphase_plain_kernel, dim3((unsigned)cdiv(nk, 256)), dim3(256), 0, st, a.k, a.N, a.reverse,
-                           a.L, a.r, g.nc, a.DT, kd);
-        if (hipGetLastError() != hipSuccess) return -1;
-        hipLaunchKernelGGL(xcorr_small_kernel, dim3((unsigned)cdiv(g.nout, 256)), dim3(256), 0, st, sc, g.nbp, kd,
-                           g.nc, a.L, a.r, g.nout, a.y);
-        return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     // step 2
     {
@@ -593,36 +499,80 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
     return 0;
 }
 
+// Block rate.  Blocks of at most kSmallL samples: one launch (corr.hip).
+// Longer blocks: the computed samples are
+//   yd[a] = sum_c sum_t s[(a + c)L + t] sum_{l<r} C[t, l] sum_u D[l, u] k'(cL + u),
+// contracted either as (s C)(D k) -- the projected signal rows against the
+// projected kernel blocks, r channels -- or as s (C D k) -- the raw signal's
+// L polyphase rows against the kernel blocks reconstructed from their first r
+// projections, L channels and no projection of the signal.  The second is
+// used when it costs fewer operations, counting the signal projection (on the
+// matrix cores) at half the cost per product of the vector ALUs.
 ConvBlockGeom conv_block_geom(int64_t W, int64_t N, int L, int r)
 {
     ConvBlockGeom g;
     g.nout = W - N + 1;
     g.nd = (g.nout - 1) / L + 1;
     g.ncb = cdiv(N, L);
+    g.ntp = rup(g.ncb, 8);
     g.nbp = rup(g.nd + g.ncb, 128);
-    g.sc_bytes = rup((int64_t)r * g.nbp * 4, 256);
-    g.kd_bytes = rup((int64_t)r * g.ncb * 4, 256);
-    g.yd_bytes = rup(g.nd * 4, 256);
-    g.total = g.sc_bytes + g.kd_bytes + g.yd_bytes;
+    g.sc_bytes = g.h_bytes = g.part_bytes = 0;
+    g.nsplit = 1;
+    if (L <= kSmallL) {
+        g.form = BF_SMALL;
+        g.nch = r;
+        g.total = 256;
+        return g;
+    }
+    const bool direct = (int64_t)r * (2 * g.ncb + L) >= 2 * (int64_t)L * g.ncb;
+    g.form = direct ? BF_DIRECT : BF_PROJECTED;
+    g.nch = direct ? L : r;
+    // enough channel ranges for about four workgroups per CU, at least 8
+    // channels (two per wave) each
+    const int64_t tiles = cdiv(g.nd, corr_rows_per_tile());
+    int64_t ns = std::min<int64_t>(cdiv(1024, tiles), g.nch / 8);
+    g.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ns, 64));
+    if (!direct) g.sc_bytes = rup((int64_t)r * g.nbp * 4, 256);
+    g.h_bytes = rup((int64_t)g.nch * g.ntp * 4, 256);
+    g.part_bytes = rup((int64_t)g.nsplit * g.nd * 4, 256);     // per-range sums of the computed samples
+    g.total = g.sc_bytes + g.h_bytes + g.part_bytes;
     return g;
 }
 
 int launch_conv_block(const ConvArgs& a, hipStream_t st)
 {
     const ConvBlockGeom g = conv_block_geom(a.W, a.N, a.L, a.r);
+    if (g.form == BF_SMALL) {
+        CorrSmallArgs c;
+        c.s = a.s; c.W = a.W; c.period = 0;
+        c.k = a.k; c.N = a.N; c.reverse = a.reverse;
+        c.L = a.L; c.r = a.r; c.C = a.C; c.DT = a.DT;
+        c.nrows = g.nd; c.ntap = g.ncb; c.nout = g.nout;
+        c.y = a.y; c.block = 1;
+        return launch_corr_small(c, st);
+    }
     float* sc = (float*)a.ws;
-    float* kd0 = (float*)((char*)a.ws + g.sc_bytes);
-    float* yd = (float*)((char*)a.ws + g.sc_bytes + g.kd_bytes);
-    if (launch_sig_project(a, sc, g.nbp, st) != 0) return -1;
-    hipLaunchKernelGGL(kblock_kernel, dim3((unsigned)cdiv((int64_t)a.r * g.ncb, 256)), dim3(256), 0, st, a.k, a.N,
-                       a.reverse, a.L, a.r, g.ncb, a.DT, kd0);
-    if (hipGetLastError() != hipSuccess) return -1;
-    hipLaunchKernelGGL(xcorr_block_kernel, dim3((unsigned)cdiv(g.nd, 256)), dim3(256), 0, st, sc, g.nbp, kd0, g.ncb,
-                       a.r, g.nd, yd);
-    if (hipGetLastError() != hipSuccess) return -1;
-    hipLaunchKernelGGL(interp_kernel, dim3((unsigned)cdiv(g.nout, 256)), dim3(256), 0, st, yd, g.nd, a.L, g.nout,
-                       a.y);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    float* h = (float*)((char*)a.ws + g.sc_bytes);
+    float* part = (float*)((char*)a.ws + g.sc_bytes + g.h_bytes);
+    CorrBlockArgs c;
+    c.L = a.L;
+    c.nch = g.nch;
+    c.h = h;
+    c.hld = g.ntp;
+    c.nd = g.nd;
+    c.nout = g.nout;
+    c.nsplit = g.nsplit;
+    c.part = part;
+    c.y = a.y;
+    if (g.form == BF_PROJECTED) {
+        if (launch_sig_project(a, sc, g.nbp, st) != 0) return -1;
+        if (launch_kblock_taps(a.k, a.N, a.reverse, a.L, a.r, g.ncb, g.ntp, a.DT, h, st) != 0) return -1;
+        c.x = sc; c.xld = g.nbp; c.xn = g.nbp;
+        return launch_corr_block(c, 0, st);
+    }
+    if (launch_ktilde(a.k, a.N, a.reverse, a.L, a.r, g.ncb, a.CT, a.DT, h, g.ntp, st) != 0) return -1;
+    c.x = a.s; c.xld = 0; c.xn = a.W;
+    return launch_corr_block(c, 1, st);
 }
 
 }  // namespace pj

@@ -162,12 +162,17 @@ def _check_block(pg, s, k, kind, L, r, mode="xcorr"):
 
 
 def block_bound(L, r, N, mag, safety=4.0):
-    """The computed samples sum r * ceil(N / L) products of two L-term FP32
-    dot products; the interpolation is a convex combination of two of them
-    (its own three roundings add at most 3u of the magnitude)."""
+    """The computed samples sum either r * ceil(N / L) products of two L-term
+    FP32 dot products (projected signal against projected kernel blocks) or
+    L * ceil(N / L) products of a signal sample with a kernel value rebuilt
+    from its projections (an L-term and an r-term dot product); the bound
+    takes the longer sum.  The interpolation is a convex combination of two
+    computed samples (its own three roundings add at most 3u of the
+    magnitude).  The magnitude sum_l |s C| |D k| is the same for both
+    groupings."""
     u = _tol.U["f32"]
     g = lambda m: m * u / (1 - m * u)
-    return safety * (2 * g(L) + g(r * -(-N // L)) + 4 * u) * mag
+    return safety * (2 * g(L) + g(L * -(-N // L)) + 4 * u) * mag
 
 
 @pytest.mark.parametrize("L", [2, 4])
