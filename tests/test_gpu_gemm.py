@@ -213,6 +213,45 @@ def test_full_size_sampled(pg, full_images, r):
         assert oracle.rel_fro(got, exact) < 1e-5
 
 
+_SAMPLE_REF = {}
+
+
+@pytest.mark.parametrize("prec,r", [("bf16", 16), ("f16", 16), ("bf16x3", 16), ("f16x3", 16), ("bf16", 64),
+                                    ("f16", 64), ("bf16x3", 64), ("fp8", 8), ("fp8x2", 8)])
+def test_full_size_sampled_reduced_precision_every_tile(pg, full_images, prec, r):
+    """The recognition workload (1024 x 8192 outputs, K = 4096, L = 64) in the
+    reduced-precision modes, packed once and contracted with EVERY tile
+    configuration (so also the one the autotuner picks for the benchmark);
+    48 x 48 sampled outputs element by element against the oracle within the
+    derived bound of the mode (FP8: plus its subnormal floor)."""
+    A, Bt = full_images
+    basis = pg.Basis("dct2", 64)
+    C, D = _ref.oracle_basis("dct2", 64)
+    M, K, W, L = 1024, 4096, 8192, 64
+    rng = np.random.default_rng(100 + r)
+    rows = np.sort(rng.choice(M, 48, replace=False))
+    cols = np.sort(rng.choice(W, 48, replace=False))
+    key = (r, tuple(rows), tuple(cols))
+    if key not in _SAMPLE_REF:
+        _SAMPLE_REF.clear()
+        _SAMPLE_REF[key] = (oracle.gemm_proj_block(A, Bt.T, C, D, r, rows, cols),
+                            oracle.gemm_proj_block(np.abs(A), np.abs(Bt.T), np.abs(C), np.abs(D), r, rows, cols))
+    ref, mag = _SAMPLE_REF[key]
+    bound = _tol.gemm_bound(prec, L, r, -(-(K // L) // KB[prec]) * KB[prec], mag)
+    if prec.startswith("fp8"):
+        bound = bound + 4.0 * _tol.fp8_floor(A[rows], np.ascontiguousarray(Bt[cols].T), C, D, r, prec)
+    Ad, Bd = _dev(A, torch.float32), _dev(Bt, torch.float32)
+    Ap, Bp = pg.pack_ab(Ad, Bd, r, basis, prec=prec, transB=True)
+    R = torch.empty((M, W), dtype=torch.float32, device="cuda")
+    ri, ci = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+    for cfg in range(len(pg.tile_configs(prec))):
+        R.fill_(float("nan"))
+        pg.gemm_packed(Ap, Bp, r, M, W, K, L, r, r, prec=prec, out=R, tile_cfg=cfg)
+        torch.cuda.synchronize()
+        got = R[ri][:, ci].double().cpu().numpy()
+        _tol.assert_within(got, ref, bound, f"full size {prec} r={r} tile_cfg={cfg}")
+
+
 @pytest.mark.parametrize("prec,r,L,K,beta", [
     ("f32", 1, 16, 65536, 0.0), ("f32", 16, 16, 65536, 0.0), ("f32", 7, 12, 60001, 0.5),
     ("bf16x3", 4, 16, 65536, 0.0), ("f16", 8, 8, 32768, 0.0), ("f64", 3, 8, 32768, -1.0), ("fp8", 8, 16, 65536, 0.0),
