@@ -21,7 +21,7 @@ import threading
 import numpy as np
 
 __all__ = [
-    "build", "lib_path", "threads",
+    "build", "lib_path", "threads", "set_threads",
     "basis_dct2", "basis_haar", "basis_identity", "basis", "invert",
     "gemm", "xcorr", "conv",
     "project_a", "project_b", "gemm_proj", "gemm_proj_block", "gemm_proj_grad",
@@ -67,6 +67,7 @@ def _load():
             p64 = ctypes.POINTER(ctypes.c_int64)
             ci = ctypes.c_int
             sig = {
+                "or_set_threads": (None, [ci]),
                 "or_basis_dct2": (None, [ci, d]),
                 "or_basis_haar": (ci, [ci, d]),
                 "or_basis_identity": (None, [ci, d]),
@@ -93,10 +94,23 @@ def _load():
     return _lib
 
 
+_threads = None
+
+
 def threads() -> int:
     """Number of OpenMP threads the oracle runs with."""
+    if _threads is not None:
+        return _threads
     n = os.environ.get("OMP_NUM_THREADS")
     return int(n) if n and n.isdigit() else (os.cpu_count() or 1)
+
+
+def set_threads(n: int) -> None:
+    """Runs the following oracle calls on n OpenMP threads (timing only; the
+    results do not depend on it: every parallel loop writes disjoint outputs)."""
+    global _threads
+    _load().or_set_threads(int(n))
+    _threads = int(n)
 
 
 def _f64(x) -> np.ndarray:

@@ -28,6 +28,20 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of OpenMP threads for the following calls (n >= 1); for timing the
+ * oracle on a given number of host cores.  No effect on any result. */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
