@@ -562,6 +562,35 @@ def main():
         cols = ["N", "r", "ms", "tflops_eq", "err_exact", "err_proj"]
         res = {"W": Wc, "L": Lc, "full_rate": table(cols, full), "block_rate": table(cols, block),
                "plain": table(["N", "ms", "tflops", "err_exact"], plain_rows)}
+        # the two realisations of the full rate on long kernels: the direct
+        # contraction and the frequency-domain one, with the library's choice
+        frows = []
+        for Lf, N, rr in [(16, 16384, 1), (16, 16384, 16), (8, 8192, 8), (32, 32768, 32), (4, 4096, 4),
+                          (16, 1024, 16), (64, 65536, 8), (256, 16384, 16)]:
+            bf = pg.Basis("dct2", Lf)
+            Cf, Df = oracle.basis("dct2", Lf)
+            k, _ = inputs.excerpt_kernel(s, N, seed=inputs.SEED_KERNEL)
+            kd = torch.from_numpy(k.astype(np.float32)).to(dev)
+            nout = Wc - N + 1
+            y = torch.empty(nout, dtype=torch.float32, device=dev)
+            msel = np.unique(np.random.default_rng(N + Lf).integers(0, nout, 61))
+            proj = oracle.xcorr_proj_at(s, k, Cf, Df, rr, msel)
+            times = {}
+            for meth in ("direct", "fft"):
+                nb = pg.conv1d_method_workspace_bytes(Wc, N, Lf, rr, meth)
+                if nb == 0:
+                    times[meth] = (None, None)
+                    continue
+                ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+                t = timed_ms(lambda: pg.conv1d_method(sd, kd, rr, bf, method=meth, out=y, workspace=ws), 5, warmup=2)
+                got = y[torch.from_numpy(msel).to(dev)].double().cpu().numpy()
+                times[meth] = (round(t, 4), f3(oracle.rel_fro(got, proj)))
+                del ws
+            auto = "fft" if pg.conv1d_method_workspace_bytes(Wc, N, Lf, rr, "auto") == \
+                pg.conv1d_method_workspace_bytes(Wc, N, Lf, rr, "fft") else "direct"
+            frows.append([Lf, N, rr, times["direct"][0], times["fft"][0], auto, times["direct"][1], times["fft"][1]])
+        res["fft_vs_direct"] = table(["L", "N", "r", "direct_ms", "fft_ms", "auto", "err_proj_direct",
+                                      "err_proj_fft"], frows)
         # circular mode on the same signal (period 2^22), N = 16384
         k, _ = inputs.excerpt_kernel(s, 16384, seed=inputs.SEED_KERNEL)
         kd = torch.from_numpy(k.astype(np.float32)).to(dev)

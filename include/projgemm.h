@@ -74,6 +74,10 @@ typedef enum {
 } pj_precision;
 
 typedef enum { PJ_XCORR = 0, PJ_CONV = 1 } pj_conv_mode;
+/* Realisation of the full-rate projected CONV: the library's choice, the
+ * direct contraction of the projected signal with the projected kernel
+ * phases, or the frequency-domain one (proj_conv1d_fft). */
+typedef enum { PJ_CONV_AUTO = 0, PJ_CONV_DIRECT = 1, PJ_CONV_FFT = 2 } pj_conv_method;
 /* Output rate of proj_conv1d_rate: every output, or only the outputs at the
  * aligned lags m = aL with the others interpolated. */
 typedef enum { PJ_RATE_FULL = 0, PJ_RATE_BLOCK = 1 } pj_conv_rate;
@@ -257,7 +261,8 @@ int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems
 
 /* ------------------------------------------- projected cross-correlation */
 
-/* Bytes of workspace proj_conv1d needs (0 for invalid arguments). */
+/* Bytes of workspace proj_conv1d needs (0 for invalid arguments); that of
+ * the realisation it picks for these sizes (see proj_conv1d_method). */
 size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec);
 
 /* Valid cross-correlation (mode PJ_XCORR) or convolution (PJ_CONV) of the
@@ -276,6 +281,44 @@ size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec);
  * Requires ws_bytes >= pj_conv1d_workspace_bytes(...). */
 int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k,
                 float* y, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* proj_conv1d with the realisation chosen by the caller (pj_conv_method).
+ * PJ_CONV_AUTO is proj_conv1d itself: it takes the frequency-domain
+ * realisation when a cost model of both (fitted to MI355X measurements; the
+ * direct cost grows with r * (N / L + 1) per output, the FFT cost with
+ * (r + L) log2 F per output row) estimates it at least 20 % faster, which
+ * happens for long kernels at small L.  Same arguments, results and errors as
+ * proj_conv1d; PJ_ERR_ARG for another method; PJ_CONV_FFT as
+ * proj_conv1d_fft.  Requires ws_bytes >=
+ * pj_conv1d_method_workspace_bytes(W, N, L, r, method, prec). */
+int proj_conv1d_method(pj_basis b, int r, int mode, int method, int64_t W, const float* s, int N,
+                       const float* k, float* y, int prec, void* ws, size_t ws_bytes, void* stream);
+size_t pj_conv1d_method_workspace_bytes(int64_t W, int N, int L, int r, int method, int prec);
+
+/* Bytes of workspace proj_conv1d_fft needs (0 for invalid arguments, or when
+ * the kernel is too long for the largest transform: more than 4096 taps per
+ * phase, (N + L - 2) / L + 1 > 4096). */
+size_t pj_conv1d_fft_workspace_bytes(int64_t W, int N, int L, int r, int prec);
+
+/* proj_conv1d's result (full rate, every output) computed in the frequency
+ * domain (paper Sec. III-A: the correlation of the projected signal with the
+ * projected kernel may use FFTs; Sec. III-C eq. (21) models its cost).  For
+ * every output phase b and projection l the T = (N + L - 2) / L + 1 taps
+ * h_{l,b}[c] = sum_u D[l, u] k'(cL - b + u) and overlapping segments of the
+ * projected signal row are transformed with F-point FFTs (F a power of two,
+ * 512 <= F <= 4096, three quarters of it left for outputs where the taps
+ * allow), the spectra are
+ * multiplied (conjugate taps) and summed over l, and one inverse transform
+ * per phase and segment gives F - T + 1 consecutive rows of outputs.  FP32
+ * throughout; the rounding error is that of the FFTs, about u log2(F) times
+ * the product of the segment's l2 norm and the taps' l1 norm, spread over all
+ * outputs (rather than the per-output bound of the direct path).  Worth it
+ * when ceil(N / L) is large and L small: the direct contraction costs about
+ * N / L products per output and projection, this one about 4 log2 F.
+ * Same arguments, errors and ownership as proj_conv1d; PJ_ERR_UNSUPPORTED when
+ * the taps do not fit.  Requires ws_bytes >= pj_conv1d_fft_workspace_bytes(...). */
+int proj_conv1d_fft(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k,
+                    float* y, int prec, void* ws, size_t ws_bytes, void* stream);
 
 /* Bytes of workspace proj_conv1d_rate needs for the given rate (0 for
  * invalid arguments).  For PJ_RATE_FULL this is pj_conv1d_workspace_bytes. */

@@ -825,21 +825,40 @@ int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W
     return PJ_OK;
 }
 
-size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec)
+size_t pj_conv1d_method_workspace_bytes(int64_t W, int N, int L, int r, int method, int prec)
 {
     if (W < 1 || N < 1 || N > W || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
+    if (method < PJ_CONV_AUTO || method > PJ_CONV_FFT) return 0;
+    if (method == PJ_CONV_FFT || (method == PJ_CONV_AUTO && conv_prefers_fft(W, N, L, r))) {
+        const ConvFftGeom g = conv_fft_geom(W, N, L, r);
+        return g.ok ? (size_t)g.total : 0;
+    }
     return (size_t)conv_geom(W, N, L, r).total;
+}
+
+size_t pj_conv1d_workspace_bytes(int64_t W, int N, int L, int r, int prec)
+{
+    return pj_conv1d_method_workspace_bytes(W, N, L, r, PJ_CONV_AUTO, prec);
 }
 
 int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k, float* y,
                 int prec, void* ws, size_t ws_bytes, void* stream)
 {
+    return proj_conv1d_method(b, r, mode, PJ_CONV_AUTO, W, s, N, k, y, prec, ws, ws_bytes, stream);
+}
+
+int proj_conv1d_method(pj_basis b, int r, int mode, int method, int64_t W, const float* s, int N, const float* k,
+                       float* y, int prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (method < PJ_CONV_AUTO || method > PJ_CONV_FFT) return PJ_ERR_ARG;
     if (!b || !s || !k || !y) return PJ_ERR_ARG;
     if (r < 1 || r > b->L) return PJ_ERR_ARG;
     if (mode != PJ_XCORR && mode != PJ_CONV) return PJ_ERR_ARG;
     if (!valid_prec(prec)) return PJ_ERR_ARG;
     if (W < 1 || N < 1 || N > W) return PJ_ERR_SHAPE;
     if (prec != PJ_F32) return PJ_ERR_UNSUPPORTED;
+    if (method == PJ_CONV_FFT || (method == PJ_CONV_AUTO && conv_prefers_fft(W, N, b->L, r)))
+        return proj_conv1d_fft(b, r, mode, W, s, N, k, y, prec, ws, ws_bytes, stream);
     const ConvGeom g = conv_geom(W, N, b->L, r);
     if (g.tiles_m * g.tiles_n > 0x7fffffff || g.k_nrb * g.k_nkb * 64 / 256 > 0x7fffffff || cdiv(g.nout, 256) > 0x7fffffff ||
         cdiv(g.nbp, 64) > 0x7fffffff || g.ncp * b->L > 0x7fffffff)
@@ -853,6 +872,38 @@ int proj_conv1d(pj_basis b, int r, int mode, int64_t W, const float* s, int N, c
     a.C = b->Cf; a.DT = b->DTf; a.CT = b->CTf;
     a.y = y; a.ws = ws;
     return launch_conv(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
+}
+
+size_t pj_conv1d_fft_workspace_bytes(int64_t W, int N, int L, int r, int prec)
+{
+    if (W < 1 || N < 1 || N > W || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
+    const ConvFftGeom g = conv_fft_geom(W, N, L, r);
+    return g.ok ? (size_t)g.total : 0;
+}
+
+int proj_conv1d_fft(pj_basis b, int r, int mode, int64_t W, const float* s, int N, const float* k, float* y,
+                    int prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!b || !s || !k || !y) return PJ_ERR_ARG;
+    if (r < 1 || r > b->L) return PJ_ERR_ARG;
+    if (mode != PJ_XCORR && mode != PJ_CONV) return PJ_ERR_ARG;
+    if (!valid_prec(prec)) return PJ_ERR_ARG;
+    if (W < 1 || N < 1 || N > W) return PJ_ERR_SHAPE;
+    if (prec != PJ_F32) return PJ_ERR_UNSUPPORTED;
+    const ConvFftGeom g = conv_fft_geom(W, N, b->L, r);
+    if (!g.ok) return PJ_ERR_UNSUPPORTED;
+    if ((int64_t)r * b->L > 0x7fffffff || (int64_t)r * g.nseg > 0x7fffffff || (int64_t)b->L * g.nseg > 0x7fffffff ||
+        cdiv(g.nseg, 2) > 65535 || cdiv(g.nbp, 128) > 0x7fffffff)
+        return PJ_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < (size_t)g.total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    ConvArgs a;
+    a.s = s; a.W = W; a.k = k; a.N = N;
+    a.reverse = (mode == PJ_CONV);
+    a.L = b->L; a.r = r;
+    a.C = b->Cf; a.DT = b->DTf; a.CT = b->CTf;
+    a.y = y; a.ws = ws;
+    return launch_conv_fft(a, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
 }
 
 size_t pj_conv1d_circular_workspace_bytes(int64_t W, int N, int L, int r, int prec)

@@ -35,6 +35,22 @@ struct ConvArgs {
                           // length of the periodic extension that the outputs read
 };
 int launch_conv(const ConvArgs& a, hipStream_t s);
+// Step 1 alone: sc[l][i] = sum_t s[iL + t] C[t, l] for l < r, i < nbp (zero past
+// the signal), rows of length nbp.
+int launch_conv_signal_rows(const ConvArgs& a, float* sc, int64_t nbp, hipStream_t s);
+
+// The same full-rate result through F-point FFTs (fft.hip): overlap-save
+// segments of P = F - T + 1 output rows, T = (N + L - 2) / L + 1 taps per phase.
+struct ConvFftGeom {
+    int64_t nout, rows, T;
+    int F, logF;
+    int64_t P, nseg, nbp;
+    bool ok;                 // T fits the largest transform with P >= 1
+    int64_t sc_bytes, tw_bytes, hf_bytes, sf_bytes, yf_bytes, total;
+};
+ConvFftGeom conv_fft_geom(int64_t W, int64_t N, int L, int r);
+int launch_conv_fft(const ConvArgs& a, hipStream_t s);
+bool conv_prefers_fft(int64_t W, int64_t N, int L, int r);   // the choice proj_conv1d makes
 
 // Block rate: outputs at m = aL only (nd of them), the rest interpolated.
 enum BlockForm {

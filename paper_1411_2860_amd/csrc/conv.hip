@@ -425,6 +425,11 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
 }
 
 // Step 1 for both rates: sc_l[i] for l < r, i < nbp.
+static int launch_sig_project(const ConvArgs& a, float* sc, int64_t nbp, hipStream_t st);
+int launch_conv_signal_rows(const ConvArgs& a, float* sc, int64_t nbp, hipStream_t st)
+{
+    return launch_sig_project(a, sc, nbp, st);
+}
 static int launch_sig_project(const ConvArgs& a, float* sc, int64_t nbp, hipStream_t st)
 {
     if (a.L > kMaxConvL) return -2;

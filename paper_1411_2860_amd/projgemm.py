@@ -16,7 +16,8 @@ import numpy as np
 __all__ = [
     "ProjGemmError", "lib", "lib_path", "Basis", "PREC", "BASIS",
     "gemm", "gemm_noalloc", "pack_a", "pack_b", "pack_ab", "tile_configs", "gemm_packed", "packed_bytes", "gemm_workspace_bytes",
-    "conv1d", "conv1d_workspace_bytes", "gemm_backward", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
+    "conv1d", "conv1d_workspace_bytes", "conv1d_fft", "conv1d_fft_workspace_bytes", "conv1d_method",
+    "conv1d_method_workspace_bytes", "gemm_backward", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
     "status_str",
 ]
 
@@ -80,6 +81,10 @@ _SIGNATURES = {
     "pj_basis_create_klt": (_i, [ctypes.POINTER(_vp), _i, _dp, _dp]),
     "pj_sym_eig": (_i, [_i, _dp, _dp, _dp]),
     "proj_conv1d_rate": (_i, [_vp, _i, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
+    "pj_conv1d_fft_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i]),
+    "pj_conv1d_method_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i, _i]),
+    "proj_conv1d_method": (_i, [_vp, _i, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
+    "proj_conv1d_fft": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
 }
 
 
@@ -381,6 +386,55 @@ def conv1d(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, works
     _check(lib().proj_conv1d_rate(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], _RATES[rate], Wn, _ptr(s), N,
                                   _ptr(k), _ptr(out), _prec(prec), _ptr(workspace), workspace.numel(),
                                   _stream(stream)), "proj_conv1d_rate")
+    return out
+
+
+METHODS = {"auto": 0, "direct": 1, "fft": 2}
+
+
+def conv1d_method_workspace_bytes(W: int, N: int, L: int, r: int, method="auto", prec="f32") -> int:
+    return int(lib().pj_conv1d_method_workspace_bytes(W, N, L, r, METHODS[method], _prec(prec)))
+
+
+def conv1d_method(s, k, r: int, basis: Basis, method="auto", mode="xcorr", prec="f32", out=None, workspace=None,
+                  stream=None):
+    """conv1d (full rate) with the realisation chosen: 'auto' (the library's
+    cost model), 'direct' or 'fft' (proj_conv1d_method)."""
+    import torch
+    Wn, N = s.numel(), k.numel()
+    if s.dtype != torch.float32 or k.dtype != torch.float32:
+        raise TypeError("s and k must be float32")
+    if not (s.is_contiguous() and k.is_contiguous()):
+        raise ValueError("s and k must be contiguous")
+    if out is None:
+        out = torch.empty(max(Wn - N + 1, 1), dtype=torch.float32, device=s.device)
+    if workspace is None:
+        workspace = _byte_buffer(conv1d_method_workspace_bytes(Wn, N, basis.L, r, method, prec), s.device)
+    _check(lib().proj_conv1d_method(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], METHODS[method], Wn, _ptr(s), N,
+                                    _ptr(k), _ptr(out), _prec(prec), _ptr(workspace), workspace.numel(),
+                                    _stream(stream)), "proj_conv1d_method")
+    return out
+
+
+def conv1d_fft_workspace_bytes(W: int, N: int, L: int, r: int, prec="f32") -> int:
+    return int(lib().pj_conv1d_fft_workspace_bytes(W, N, L, r, _prec(prec)))
+
+
+def conv1d_fft(s, k, r: int, basis: Basis, mode="xcorr", prec="f32", out=None, workspace=None, stream=None):
+    """conv1d (full rate) through FFTs of the projected signal segments and
+    the projected kernel phases (proj_conv1d_fft)."""
+    import torch
+    Wn, N = s.numel(), k.numel()
+    if s.dtype != torch.float32 or k.dtype != torch.float32:
+        raise TypeError("s and k must be float32")
+    if not (s.is_contiguous() and k.is_contiguous()):
+        raise ValueError("s and k must be contiguous")
+    if out is None:
+        out = torch.empty(max(Wn - N + 1, 1), dtype=torch.float32, device=s.device)
+    if workspace is None:
+        workspace = _byte_buffer(conv1d_fft_workspace_bytes(Wn, N, basis.L, r, prec), s.device)
+    _check(lib().proj_conv1d_fft(basis.handle, r, {"xcorr": 0, "conv": 1}[mode], Wn, _ptr(s), N, _ptr(k), _ptr(out),
+                                 _prec(prec), _ptr(workspace), workspace.numel(), _stream(stream)), "proj_conv1d_fft")
     return out
 
 

@@ -175,6 +175,20 @@ def test_noalloc_validation_and_scratch_limit(lib, basis16):
     assert "#define PJ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in text
 
 
+def test_conv_picks_fft_for_long_kernels(lib):
+    """proj_conv1d takes the frequency-domain path when its cost model says so
+    (its workspace query then returns the FFT path's size): long kernels at
+    small L, not short kernels or L = 256 with a few projections."""
+    W = 1 << 22
+    fft = lambda N, L, r: lib.pj_conv1d_fft_workspace_bytes(W, N, L, r, 1)
+    conv = lambda N, L, r: lib.pj_conv1d_workspace_bytes(W, N, L, r, 1)
+    assert conv(16384, 16, 16) == fft(16384, 16, 16) > 0
+    assert conv(8192, 8, 8) == fft(8192, 8, 8) > 0
+    for N, L, r in [(16384, 256, 16), (1024, 256, 1), (600, 2, 1), (64, 4, 4)]:
+        assert conv(N, L, r) != fft(N, L, r)
+    assert fft(8192, 2, 1) == 0                   # 4097 taps per phase: beyond the transform
+
+
 def test_pack_and_packed_gemm_validation(lib, basis16):
     b = basis16
     n = pg.packed_bytes(8, 32, 16, 4)

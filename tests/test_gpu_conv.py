@@ -288,3 +288,121 @@ def test_circular_full_size_sampled(pg, long_signal, r):
     ref = oracle.xcorr_proj_at(ext, k, C, D, r, ms)
     mag = oracle.xcorr_proj_at(np.abs(ext), np.abs(k), np.abs(C), np.abs(D), r, ms)
     _tol.assert_within(got, ref, conv_bound(L, r, N, mag), f"circular full size r={r}")
+
+
+# ---- frequency domain (FFT) realisation of the full rate ----------------------
+
+def _fft_geom(W, N, L):
+    T = (N + L - 2) // L + 1
+    F = 512
+    while F < 4096 and 4 * (F - T + 1) < 3 * F:
+        F *= 2
+    return T, F, F - T + 1
+
+
+def fft_bound(s, k, C, D, L, r, mag):
+    """Rounding of the FFT path per output m = (sP + a)L + b: the projected
+    signal rows and kernel taps carry their L-term FP32 dot products (as in
+    the direct path), and the F-point transforms of segment s and taps
+    h_{l,b}, their product and the inverse transform add about
+    u log2(F) ||x_{l,s}||_2 ||h_{l,b}||_1 per projection (the DFT is unitary
+    up to sqrt(F), |H| <= ||h||_1); used with a safety factor of 8."""
+    u = _tol.U["f32"]
+    g = lambda m: m * u / (1 - m * u)
+    W, N = s.size, k.size
+    T, F, P = _fft_geom(W, N, L)
+    nout = W - N + 1
+    rows = -(-nout // L)
+    nseg = -(-rows // P)
+    nb = nseg * P + F
+    sc = np.zeros((r, nb))
+    pj = oracle.project_signal(s, C, r)
+    sc[:, :min(nb, pj.shape[1])] = pj[:, :nb]
+    seg = np.array([[np.linalg.norm(sc[l, i * P:i * P + F]) for i in range(nseg)] for l in range(r)])
+    kd = oracle.project_kernel(k, D, r)                  # kd[l][q + L - 1], q = -(L - 1) .. N - 1
+    h1 = np.zeros((r, L))
+    for b in range(L):
+        q = np.arange(T) * L - b + L - 1
+        ok = (q >= 0) & (q < kd.shape[1])
+        h1[:, b] = np.abs(kd[:, q[ok]]).sum(axis=1)
+    m = np.arange(nout)
+    sidx, b = (m // L) // P, m % L
+    fftpart = 8.0 * u * (3 * np.log2(F) + 4) * (seg[:, sidx] * h1[:, b]).sum(axis=0)
+    return fftpart + 4.0 * (2 * g(L) + u) * mag
+
+
+def _check_fft(pg, s, k, kind, L, r, mode="xcorr"):
+    basis = pg.Basis(kind, L)
+    C, D = _ref.oracle_basis(kind, L)
+    y = pg.conv1d_fft(_dev(s), _dev(k), r, basis, mode=mode)
+    torch.cuda.synchronize()
+    got = y.double().cpu().numpy()
+    kk = k[::-1] if mode == "conv" else k
+    ref = oracle.xcorr_proj(s, kk, C, D, r)
+    mag = oracle.xcorr_proj(np.abs(s), np.abs(kk), np.abs(C), np.abs(D), r)
+    _tol.assert_within(got, ref, fft_bound(s, kk, C, D, L, r, mag), f"fft {kind} L={L} r={r} N={k.size} {mode}")
+    return got, ref
+
+
+@pytest.mark.parametrize("r", [1, 4, 16])
+def test_fft_long_kernel(pg, r):
+    """N / L = 1024 (L = 16, N = 16384 on 2^18 samples of the AR(2) process):
+    every output against the oracle; 4096-point transforms, 3072 rows per
+    segment (86 segments); at r = L the exact cross-correlation within 1e-5."""
+    s = inputs.ar2_signal(1 << 18, seed=31)
+    k, _ = inputs.excerpt_kernel(s, 16384, seed=32)
+    got, ref = _check_fft(pg, s, k, "dct2", 16, r)
+    if r == 16:
+        assert oracle.rel_fro(got, np.correlate(s, k, "valid")) < 1e-5
+
+
+@pytest.mark.parametrize("W,N,L,kind,r", [
+    (3000, 100, 4, "haar", 2),       # 512-point transforms, many segments, ragged end
+    (5000, 777, 5, "dct2", 3),       # L not a power of two
+    (4096, 4096, 8, "dct2", 8),      # one output
+    (2049, 2048, 1, "identity", 1),  # L = 1: the plain correlation, 2048 taps
+    (70000, 30000, 32, "dct2", 7),   # 938 taps per phase
+])
+def test_fft_ragged(pg, W, N, L, kind, r):
+    rng = np.random.default_rng(W + N)
+    s, k = rng.standard_normal(W), rng.standard_normal(N)
+    _check_fft(pg, s, k, kind, L, r)
+
+
+def test_fft_convolution_mode_and_direct_path_agree(pg):
+    s = inputs.ar2_signal(20000, seed=33)
+    k, _ = inputs.excerpt_kernel(s, 1200, seed=34)
+    got, ref = _check_fft(pg, s, k, "haar", 2, 1, mode="conv")
+    basis = pg.Basis("haar", 2)
+    direct = pg.conv1d(_dev(s), _dev(k), 1, basis, mode="conv")
+    torch.cuda.synchronize()
+    assert oracle.rel_fro(got, direct.double().cpu().numpy()) < 1e-5
+
+
+def test_fft_rejects_taps_beyond_transform(pg):
+    basis = pg.Basis("dct2", 2)
+    assert pg.conv1d_fft_workspace_bytes(1 << 16, 8192, 2, 1) == 0       # 4097 taps per phase
+    with pytest.raises(pg.ProjGemmError, match="UNSUPPORTED"):
+        s = torch.zeros(1 << 16, device="cuda")
+        pg.conv1d_fft(s, torch.zeros(8192, device="cuda"), 1, basis, workspace=torch.empty(256, dtype=torch.uint8,
+                                                                                           device="cuda"))
+
+
+def test_auto_picks_fft_and_direct_still_exact(pg):
+    """L = 16, N = 16384 on 2^18 samples, r = 4: the library's choice is the
+    frequency-domain path (bit for bit the proj_conv1d_fft result); the direct
+    contraction, asked for explicitly, stays within its own bound."""
+    s = inputs.ar2_signal(1 << 18, seed=35)
+    k, _ = inputs.excerpt_kernel(s, 16384, seed=36)
+    L, r = 16, 4
+    basis = pg.Basis("dct2", L)
+    C, D = _ref.oracle_basis("dct2", L)
+    sd, kd = _dev(s), _dev(k)
+    auto = pg.conv1d(sd, kd, r, basis)
+    fft = pg.conv1d_fft(sd, kd, r, basis)
+    direct = pg.conv1d_method(sd, kd, r, basis, method="direct")
+    torch.cuda.synchronize()
+    assert torch.equal(auto, fft)
+    ref = oracle.xcorr_proj(s, k, C, D, r)
+    mag = oracle.xcorr_proj(np.abs(s), np.abs(k), np.abs(C), np.abs(D), r)
+    _tol.assert_within(direct.double().cpu().numpy(), ref, conv_bound(L, r, k.size, mag), "direct at N/L = 1024")
