@@ -379,9 +379,12 @@ __global__ __launch_bounds__(256) void split_sum_kernel(const float* __restrict_
     y[m] = v;
 }
 
-// tile shapes: 128 x 256 (8 waves) when L > 128, else 128 x 128 (4 waves)
-constexpr int XW_M = 2, XW_N = 2, XWAVES_M = 2;
-constexpr int XBM = 32 * XW_M * XWAVES_M;
+// Tile shapes by block length, so that the phase tile covers the L phases
+// with at most half of it padding: 128 rows x 256 phases (8 waves) for
+// L > 128, 128 x 128 for L > 64, 128 x 64 for L > 32 and 256 x 32 for L <= 32
+// (4 waves each).
+constexpr int xcorr_bm(int L) { return L <= 32 ? 256 : 128; }
+constexpr int xcorr_bnb(int L) { return L > 128 ? 8 : L > 64 ? 4 : L > 32 ? 2 : 1; }
 // Splits of the contraction: enough for one workgroup per CU (256) with at
 // least 32 k-blocks each, and up to 512 workgroups with at least 64 each
 // (more splits cost a pass over their partial outputs).
@@ -398,12 +401,12 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
     g.nc = (N + L - 2) / L + 1;
     g.ncp = rup(g.nc, 4);
     g.rows = cdiv(g.nout, L);                       // output rows a
-    g.tiles_m = cdiv(g.rows, XBM);
-    g.nbp = rup(g.tiles_m * XBM + g.ncp, 64);       // projected-signal row length
+    const int bm = xcorr_bm(L);
+    g.tiles_m = cdiv(g.rows, bm);
+    g.nbp = rup(g.tiles_m * bm + g.ncp, 64);        // projected-signal row length
     g.k_nrb = cdiv(L, 32);
     g.k_nkb = cdiv((int64_t)r * g.ncp, 8);
-    const int bnb = L > 128 ? 8 : 4;
-    g.tiles_n = cdiv(g.k_nrb, bnb);
+    g.tiles_n = cdiv(g.k_nrb, xcorr_bnb(L));
     g.small = L <= kSmallL;
     const int64_t tiles = g.tiles_m * g.tiles_n;
     const int64_t t1 = std::max<int64_t>(1, tiles);
@@ -489,11 +492,17 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
         float* part = (float*)((char*)a.ws + g.sc_bytes + g.k_bytes);
         dim3 grid((unsigned)(g.tiles_m * g.tiles_n), (unsigned)g.nsplit);
         if (a.L > 128)
-            hipLaunchKernelGGL((xcorr_kernel<XW_M, XW_N, XWAVES_M, 4>), grid, dim3(64 * XWAVES_M * 4), 0, st, sc, g.nbp,
-                               kp, g.k_nrb, g.k_nkb, g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
+            hipLaunchKernelGGL((xcorr_kernel<2, 2, 2, 4>), grid, dim3(512), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb,
+                               g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
+        else if (a.L > 64)
+            hipLaunchKernelGGL((xcorr_kernel<2, 2, 2, 2>), grid, dim3(256), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb,
+                               g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
+        else if (a.L > 32)
+            hipLaunchKernelGGL((xcorr_kernel<2, 1, 2, 2>), grid, dim3(256), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb,
+                               g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
         else
-            hipLaunchKernelGGL((xcorr_kernel<XW_M, XW_N, XWAVES_M, 2>), grid, dim3(64 * XWAVES_M * 2), 0, st, sc, g.nbp,
-                               kp, g.k_nrb, g.k_nkb, g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
+            hipLaunchKernelGGL((xcorr_kernel<2, 1, 4, 1>), grid, dim3(256), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb,
+                               g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
         if (hipGetLastError() != hipSuccess) return -1;
         if (g.nsplit > 1) {
             hipLaunchKernelGGL(split_sum_kernel, dim3((unsigned)cdiv(g.nout, 256)), dim3(256), 0, st, part, g.nsplit,

@@ -204,8 +204,8 @@ ConvFftGeom conv_fft_geom(int64_t W, int64_t N, int L, int r)
 // Which realisation proj_conv1d uses: estimated times (fitted to measurements
 // on MI355X) of the direct path -- the one-launch vector-ALU kernel for L <= 8
 // (W r T products at about 2e13 per second), otherwise the matrix-core
-// implicit GEMM over a phase tile of 128 (L <= 128) or 256 after two small
-// launches -- and of the FFT path (six launches; about 0.12 ms + 0.004 ms per
+// implicit GEMM over a phase tile of 32, 64, 128 or 256 (the power of two
+// covering L, at least 32) after two small launches -- and of the FFT path (six launches; about 0.12 ms + 0.004 ms per
 // signal row and phase, r + L, per 2^22 samples, scaled by the share of each
 // transform that is output); the FFT path is taken when it is estimated at
 // least 20 % faster.
@@ -214,12 +214,12 @@ bool conv_prefers_fft(int64_t W, int64_t N, int L, int r)
     const ConvFftGeom f = conv_fft_geom(W, N, L, r);
     if (!f.ok || f.T < 16) return false;
     const double scale = (double)W / 4194304.0;
-    const double t_fft = 30e-6 + scale * (0.12e-3 + 0.004e-3 * (r + L)) * (4.0 * f.F / (3.0 * f.P));
+    const double t_fft = 30e-6 + scale * (0.12e-3 + 0.004e-3 * (r + L)) * (3.0 * f.F / (4.0 * f.P));
     double t_direct;
     if (L <= 8) {
         t_direct = 8e-6 + (double)W * r * f.T / 2.0e13;
     } else {
-        const double bn = L <= 128 ? 128.0 : 256.0;
+        const double bn = L > 128 ? 256.0 : L > 64 ? 128.0 : L > 32 ? 64.0 : 32.0;   // phase tile
         t_direct = 25e-6 + 2.0 * ((double)W / L) * bn * r * f.T / 1.0e14;
     }
     return t_fft < 0.8 * t_direct;
