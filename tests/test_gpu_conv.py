@@ -406,3 +406,21 @@ def test_auto_picks_fft_and_direct_still_exact(pg):
     ref = oracle.xcorr_proj(s, k, C, D, r)
     mag = oracle.xcorr_proj(np.abs(s), np.abs(k), np.abs(C), np.abs(D), r)
     _tol.assert_within(direct.double().cpu().numpy(), ref, conv_bound(L, r, k.size, mag), "direct at N/L = 1024")
+
+
+@pytest.mark.parametrize("L", [12, 24, 32, 48, 64, 96, 128, 200])
+def test_direct_phase_tiles_mid_L(pg, L):
+    """The direct contraction's phase tile follows L (32, 64, 128 or 256 phases
+    per tile, 256 or 128 rows): every output against the oracle, L not
+    necessarily a power of two, for r = 1, L / 2 and L."""
+    rng = np.random.default_rng(L)
+    W, N = 7 * L * 37 + 5, 5 * L + 3
+    s, k = rng.standard_normal(W), rng.standard_normal(N)
+    basis = pg.Basis("dct2", L)
+    C, D = _ref.oracle_basis("dct2", L)
+    for r in sorted({1, L // 2, L}):
+        y = pg.conv1d_method(_dev(s), _dev(k), r, basis, method="direct")
+        torch.cuda.synchronize()
+        ref = oracle.xcorr_proj(s, k, C, D, r)
+        mag = oracle.xcorr_proj(np.abs(s), np.abs(k), np.abs(C), np.abs(D), r)
+        _tol.assert_within(y.double().cpu().numpy(), ref, conv_bound(L, r, N, mag), f"direct L={L} r={r}")
