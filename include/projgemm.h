@@ -227,6 +227,38 @@ int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W
                        const void* dR, int64_t lddr, void* dA, int64_t ldda, void* dB, int64_t lddb,
                        int prec, void* ws, size_t ws_bytes, void* stream);
 
+/* Bytes of the plain projections proj_gemm_save keeps (0 for invalid
+ * arguments): A_hat (M x r*Gp) then, at the next 256-byte boundary, B_hat
+ * (W x r*Gp), row-major, element (p, l*Gp + j) = projection l of group j of
+ * row p, Gp = ceil(K / L) rounded up to the precision's k-block (16 for the
+ * 16-bit formats, 64 for FP8, 8 otherwise); double for PJ_F64, else float. */
+size_t pj_gemm_saved_bytes(int M, int W, int K, int L, int r, int prec);
+
+/* proj_gemm that also writes the plain projections A C_N and D_N B of its
+ * pack step (paper Sec. III-B, the projected operands of eq. (8)) into
+ * `saved` (pj_gemm_saved_bytes, caller-owned device memory), so that
+ * proj_gemm_backward_saved pays the projection cost of eq. (17) once per
+ * operand instead of again in the backward.  The values are the ones the
+ * contraction consumed, before their conversion to `prec`.  Errors as
+ * proj_gemm, plus PJ_ERR_ARG for a NULL `saved` and PJ_ERR_WORKSPACE when
+ * saved_bytes is too small. */
+int proj_gemm_save(pj_basis b, int r, char transA, char transB, int M, int W, int K,
+                   const void* A, int64_t lda, const void* B, int64_t ldb,
+                   float beta, void* R, int64_t ldr, int prec, void* ws, size_t ws_bytes,
+                   void* saved, size_t saved_bytes, void* stream);
+
+/* Bytes of workspace proj_gemm_backward_saved needs (0 for invalid arguments). */
+size_t pj_gemm_backward_saved_workspace_bytes(int M, int W, int K, int L, int r, int prec);
+
+/* proj_gemm_backward from the projections a proj_gemm_save call with the same
+ * basis, r, shapes and prec kept: the same two reduced contractions and
+ * syntheses, without re-projecting A and B.  `saved` is read only.  Errors
+ * as proj_gemm_backward; PJ_ERR_WORKSPACE when saved_bytes is too small. */
+int proj_gemm_backward_saved(pj_basis b, int r, char transA, char transB, int M, int W, int K,
+                             const void* saved, size_t saved_bytes,
+                             const void* dR, int64_t lddr, void* dA, int64_t ldda, void* dB, int64_t lddb,
+                             int prec, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------- batched projected GEMM */
 
 /* One problem of a batch: R <- A Q_{r,K} B + beta R with proj_gemm's

@@ -1,8 +1,9 @@
-"""Differentiable projected GEMM: torch.autograd.Function over proj_gemm and
-proj_gemm_backward.
+"""Differentiable projected GEMM: torch.autograd.Function over proj_gemm_save and
+proj_gemm_backward_saved.
 
-Forward: R = A Q_{r,K} B (paper Sec. III-A/B).  Backward (hand-written, in the
-library's kernels): dA = dR (D_N B)_r^T C_N^T and dB = D_N^T (A C_N)_r^T dR,
+Forward: R = A Q_{r,K} B (paper Sec. III-A/B), keeping the projections of
+its pack step.  Backward (hand-written, in the library's kernels, on those
+kept projections): dA = dR (D_N B)_r^T C_N^T and dB = D_N^T (A C_N)_r^T dR,
 each one reduced contraction over r * ceil(K / L) projected indices followed
 by a synthesis over the groups.  With an orthonormal basis (DCT-II, Haar)
 C_N = D_N^T = P, so dA = dR B^T P P^T: the gradient of A is the exact gradient
@@ -23,20 +24,26 @@ class ProjGemmFn(torch.autograd.Function):
         dt = torch.float64 if prec == "f64" else torch.float32
         A_ = A.to(dt).contiguous()
         B_ = B.to(dt).contiguous()
-        R = pg.gemm(A_, B_, r, basis, prec=prec)
-        ctx.save_for_backward(A_, B_)
+        # the pack step keeps its plain projections A C_N and D_N B, so the
+        # backward contracts against them instead of projecting A and B again
+        R, saved = pg.gemm_save(A_, B_, r, basis, prec=prec)
+        ctx.save_for_backward(saved)
         ctx.r, ctx.basis, ctx.prec = r, basis, prec
+        ctx.shape = (A_.shape[0], B_.shape[1], A_.shape[1])
         ctx.in_dtypes = (A.dtype, B.dtype)
         return R.to(A.dtype) if A.dtype != dt else R
 
     @staticmethod
     def backward(ctx, dR):
-        A_, B_ = ctx.saved_tensors
+        (saved,) = ctx.saved_tensors
         need_a, need_b = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (need_a or need_b):
             return None, None, None, None, None
-        dR_ = dR.to(A_.dtype).contiguous()
-        dA, dB = pg.gemm_backward(A_, B_, dR_, ctx.r, ctx.basis, prec=ctx.prec, need_dA=need_a, need_dB=need_b)
+        dt = torch.float64 if ctx.prec == "f64" else torch.float32
+        dR_ = dR.to(dt).contiguous()
+        M, W, K = ctx.shape
+        dA, dB = pg.gemm_backward_saved(saved, dR_, ctx.r, ctx.basis, M, W, K, prec=ctx.prec, need_dA=need_a,
+                                        need_dB=need_b, dtype=dt)
         if dA is not None:
             dA = dA.to(ctx.in_dtypes[0])
         if dB is not None:

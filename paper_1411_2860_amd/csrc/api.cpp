@@ -466,6 +466,23 @@ static int gemm_packed_impl(int r, int M, int W, int K, int L, int prec, const v
     return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
 }
 
+// Plain projections kept by proj_gemm_save: A_hat (M x rG) then B_hat
+// (W x rG), rG = r * Gp with the packed geometry's Gp, FP64 for PJ_F64.
+struct SavedGeom {
+    int64_t Gp, rg;
+    size_t bhat, total;
+};
+static SavedGeom saved_geom(int M, int W, int K, int L, int r, int prec)
+{
+    SavedGeom g;
+    g.Gp = pack_geom(1, K, L, r, prec).Gp;
+    g.rg = (int64_t)r * g.Gp;
+    const int64_t T = prec == PJ_F64 ? 8 : 4;
+    g.bhat = align256((size_t)M * g.rg * T);
+    g.total = g.bhat + align256((size_t)W * g.rg * T);
+    return g;
+}
+
 // Argument checks of proj_gemm (host only, before any device work).
 static int check_proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A,
                            int64_t lda, const void* B, int64_t ldb, const void* R, int64_t ldr, int prec)
@@ -487,13 +504,19 @@ static int check_proj_gemm(pj_basis b, int r, char transA, char transB, int M, i
 // least pj_gemm_workspace_bytes: pack both sides, then contract.
 static int run_proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A,
                          int64_t lda, const void* B, int64_t ldb, float beta, void* R, int64_t ldr, int prec,
-                         void* ws, void* stream)
+                         void* ws, void* stream, void* keep = nullptr)
 {
     char* wa = (char*)ws;
     char* wb = wa + align256(pj_packed_bytes(M, K, b->L, r, prec));
     char* wp = wb + align256(pj_packed_bytes(W, K, b->L, r, prec));
     PackArgs pa[2] = {pack_args(b, r, true, transA, M, K, A, lda, prec, wa),
                       pack_args(b, r, false, transB, W, K, B, ldb, prec, wb)};
+    if (keep) {
+        const SavedGeom sg = saved_geom(M, W, K, b->L, r, prec);
+        pa[0].keep = keep;
+        pa[1].keep = (char*)keep + sg.bhat;
+        pa[0].keep_ld = pa[1].keep_ld = sg.rg;
+    }
     int rc = run_pack(prec, pa, 2, stream);
     if (rc != PJ_OK) return rc;
     const PackGeom ga = pack_geom(M, K, b->L, r, prec);
@@ -515,6 +538,26 @@ int proj_gemm(pj_basis b, int r, char transA, char transB, int M, int W, int K, 
     if (!ws || ws_bytes < need) return PJ_ERR_WORKSPACE;
     if (!b->on_device) return PJ_ERR_HIP;
     return run_proj_gemm(b, r, transA, transB, M, W, K, A, lda, B, ldb, beta, R, ldr, prec, ws, stream);
+}
+
+size_t pj_gemm_saved_bytes(int M, int W, int K, int L, int r, int prec)
+{
+    if (M < 1 || W < 1 || K < 1 || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
+    return saved_geom(M, W, K, L, r, prec).total;
+}
+
+int proj_gemm_save(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
+                   const void* B, int64_t ldb, float beta, void* R, int64_t ldr, int prec, void* ws,
+                   size_t ws_bytes, void* saved, size_t saved_bytes, void* stream)
+{
+    int rc = check_proj_gemm(b, r, transA, transB, M, W, K, A, lda, B, ldb, R, ldr, prec);
+    if (rc != PJ_OK) return rc;
+    if (!saved) return PJ_ERR_ARG;
+    if (saved_bytes < saved_geom(M, W, K, b->L, r, prec).total) return PJ_ERR_WORKSPACE;
+    const size_t need = pj_gemm_workspace_bytes(M, W, K, b->L, r, prec);
+    if (!ws || ws_bytes < need) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    return run_proj_gemm(b, r, transA, transB, M, W, K, A, lda, B, ldb, beta, R, ldr, prec, ws, stream, saved);
 }
 
 }  // extern "C"
@@ -718,20 +761,26 @@ struct BwdPlan {
     size_t p1, p2, p3, p4;
 };
 
-// Plain projections use the FP32 / FP64 fragment geometry (k-blocks of 8).
-BwdPlan plan_bwd(int M, int W, int K, int L, int r, int prec)
+// Workspace of the backward for projections of Gp padded groups; with
+// `proj` the plain projections of A and B are computed into it first (else
+// the caller's saved ones are used).  Plain projections use the FP32 / FP64
+// fragment geometry (k-blocks of 8).
+BwdPlan plan_bwd(int M, int W, int K, int L, int r, int prec, int64_t Gp, bool proj)
 {
     BwdPlan p;
     p.T = (prec == PJ_F64) ? 8 : 4;
-    p.Gp = rup(cdiv(K, L), 8);
+    p.Gp = Gp;
     p.rg = (int64_t)r * p.Gp;
     p.p1 = align256(pj_packed_bytes(M, W, 4, 4, prec));
     p.p2 = align256(pj_packed_bytes((int)p.rg, W, 4, 4, prec));
     p.p3 = align256(pj_packed_bytes((int)p.rg, M, 4, 4, prec));
     p.p4 = align256(pj_packed_bytes(W, M, 4, 4, prec));
     size_t off = 0;
-    p.ahat = off; off += align256((size_t)M * p.rg * p.T);
-    p.bhat = off; off += align256((size_t)W * p.rg * p.T);
+    p.ahat = p.bhat = 0;
+    if (proj) {
+        p.ahat = off; off += align256((size_t)M * p.rg * p.T);
+        p.bhat = off; off += align256((size_t)W * p.rg * p.T);
+    }
     p.pk = off; off += std::max(p.p1 + p.p2, p.p3 + p.p4);
     p.dahat = off; off += align256((size_t)M * p.rg * p.T);
     p.dbhat = off; off += align256((size_t)p.rg * W * p.T);
@@ -739,48 +788,32 @@ BwdPlan plan_bwd(int M, int W, int K, int L, int r, int prec)
     return p;
 }
 
-}  // namespace
+int64_t bwd_plain_gp(int K, int L) { return rup(cdiv(K, L), 8); }
 
-size_t pj_gemm_backward_workspace_bytes(int M, int W, int K, int L, int r, int prec)
+int check_bwd(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* dR, int64_t lddr,
+              void* dA, int64_t ldda, void* dB, int64_t lddb, int prec)
 {
-    if (M < 1 || W < 1 || K < 1 || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
-    return plan_bwd(M, W, K, L, r, prec).total;
-}
-
-int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
-                       const void* B, int64_t ldb, const void* dR, int64_t lddr, void* dA, int64_t ldda, void* dB,
-                       int64_t lddb, int prec, void* ws, size_t ws_bytes, void* stream)
-{
-    if (!b || !A || !B || !dR || (!dA && !dB)) return PJ_ERR_ARG;
+    if (!b || !dR || (!dA && !dB)) return PJ_ERR_ARG;
     if (!valid_prec(prec)) return PJ_ERR_ARG;
     if (r < 1 || r > b->L) return PJ_ERR_ARG;
     if ((!is_n(transA) && !is_t(transA)) || (!is_n(transB) && !is_t(transB))) return PJ_ERR_ARG;
     if (M < 1 || W < 1 || K < 1) return PJ_ERR_SHAPE;
-    if (lda < (is_n(transA) ? (int64_t)K : (int64_t)M)) return PJ_ERR_SHAPE;
-    if (ldb < (is_n(transB) ? (int64_t)W : (int64_t)K)) return PJ_ERR_SHAPE;
     if (lddr < W) return PJ_ERR_SHAPE;
     if (dA && ldda < (is_n(transA) ? (int64_t)K : (int64_t)M)) return PJ_ERR_SHAPE;
     if (dB && lddb < (is_n(transB) ? (int64_t)W : (int64_t)K)) return PJ_ERR_SHAPE;
-    const BwdPlan pl = plan_bwd(M, W, K, b->L, r, prec);
-    if (pl.rg > 0x7fffffff) return PJ_ERR_UNSUPPORTED;
-    if (!ws || ws_bytes < pl.total) return PJ_ERR_WORKSPACE;
-    if (!b->on_device) return PJ_ERR_HIP;
-    hipStream_t st = (hipStream_t)stream;
-    char* w = (char*)ws;
+    return PJ_OK;
+}
+
+// Steps 2-5 of the backward from the plain projections ahat (M x rG) and
+// bhat (W x rG), row stride rG = r * pl.Gp.
+int run_bwd(pj_basis b, int r, char transA, char transB, int M, int W, int K, const char* ahat, const char* bhat,
+            const BwdPlan& pl, const void* dR, int64_t lddr, void* dA, int64_t ldda, void* dB, int64_t lddb,
+            int prec, char* w, hipStream_t st)
+{
     const bool f64 = (prec == PJ_F64);
-    const int plain = f64 ? P_PLAIN64 : P_PLAIN32;
     const void* I4 = f64 ? (const void*)b->I4d : (const void*)b->I4f;
-
-    // 1. plain projections of A (with C) and B (with D^T): M x rG and W x rG
-    PackArgs pa[2] = {pack_args(b, r, true, transA, M, K, A, lda, plain, w + pl.ahat),
-                      pack_args(b, r, false, transB, W, K, B, ldb, plain, w + pl.bhat)};
-    pa[0].geom = pack_geom(M, K, b->L, r, plain);
-    pa[1].geom = pack_geom(W, K, b->L, r, plain);
-    pa[0].plain_ld = pa[1].plain_ld = pl.rg;
-    if (launch_pack_n(plain, pa, 2, st) != 0) return PJ_ERR_HIP;
-
-    // packs an unprojected operand: rows x Kc of src (trans as given) with
-    // the 4 x 4 identity, i.e. the contraction index merely permuted
+    // packs an unprojected operand: rows x Kc of src (trans as given), the
+    // contraction index kept as it is
     auto unproj = [&](const void* src, int64_t ld, int trans, int64_t rows, int64_t Kc, void* dst) {
         PackArgs u;
         u.X = src; u.ld = ld; u.trans = trans; u.P = rows; u.K = Kc; u.L = 4; u.r = 4;
@@ -795,11 +828,15 @@ int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W
         g.P = P; g.Q = Q; g.R = R; g.ldr = ldr; g.beta = 0.0f;
         return launch_gemm(prec, g, -1, st);
     };
+    // the unprojected operands are only re-laid out (natural contraction
+    // order); FP8 keeps the packer's identity pass for its MX scales
+    const bool fp8 = (prec == PJ_FP8 || prec == PJ_FP8X2);
+    auto pack2 = [&](const PackArgs* u) { return fp8 ? launch_pack_n(prec, u, 2, st) : launch_repack_n(prec, u, 2, st); };
     char* p1 = w + pl.pk;
     if (dA) {
         // 2. dA_hat = dR B_hat: contraction over the W columns of R
-        PackArgs u[2] = {unproj(dR, lddr, 0, M, W, p1), unproj(w + pl.bhat, pl.rg, 1, pl.rg, W, p1 + pl.p1)};
-        if (launch_pack_n(prec, u, 2, st) != 0) return PJ_ERR_HIP;
+        PackArgs u[2] = {unproj(dR, lddr, 0, M, W, p1), unproj(bhat, pl.rg, 1, pl.rg, W, p1 + pl.p1)};
+        if (pack2(u) != 0) return PJ_ERR_HIP;
         if (gemm(p1, M, p1 + pl.p1, pl.rg, W, w + pl.dahat, pl.rg) != 0) return PJ_ERR_HIP;
         // 3. dA = dA_hat spread back over each group with C
         ExpandArgs e;
@@ -811,8 +848,8 @@ int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W
     }
     if (dB) {
         // 4. dB_hat = A_hat^T dR: contraction over the M rows of R
-        PackArgs u[2] = {unproj(w + pl.ahat, pl.rg, 1, pl.rg, M, p1), unproj(dR, lddr, 1, W, M, p1 + pl.p3)};
-        if (launch_pack_n(prec, u, 2, st) != 0) return PJ_ERR_HIP;
+        PackArgs u[2] = {unproj(ahat, pl.rg, 1, pl.rg, M, p1), unproj(dR, lddr, 1, W, M, p1 + pl.p3)};
+        if (pack2(u) != 0) return PJ_ERR_HIP;
         if (gemm(p1, pl.rg, p1 + pl.p3, W, M, w + pl.dbhat, W) != 0) return PJ_ERR_HIP;
         // 5. dB = dB_hat spread back over each group with D
         ExpandArgs e;
@@ -823,6 +860,66 @@ int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W
         if (launch_expand(f64, e, st) != 0) return PJ_ERR_HIP;
     }
     return PJ_OK;
+}
+
+}  // namespace
+
+size_t pj_gemm_backward_workspace_bytes(int M, int W, int K, int L, int r, int prec)
+{
+    if (M < 1 || W < 1 || K < 1 || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
+    return plan_bwd(M, W, K, L, r, prec, bwd_plain_gp(K, L), true).total;
+}
+
+int proj_gemm_backward(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, const void* dR, int64_t lddr, void* dA, int64_t ldda, void* dB,
+                       int64_t lddb, int prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!A || !B) return PJ_ERR_ARG;
+    int rc = check_bwd(b, r, transA, transB, M, W, K, dR, lddr, dA, ldda, dB, lddb, prec);
+    if (rc != PJ_OK) return rc;
+    if (lda < (is_n(transA) ? (int64_t)K : (int64_t)M)) return PJ_ERR_SHAPE;
+    if (ldb < (is_n(transB) ? (int64_t)W : (int64_t)K)) return PJ_ERR_SHAPE;
+    const BwdPlan pl = plan_bwd(M, W, K, b->L, r, prec, bwd_plain_gp(K, b->L), true);
+    if (pl.rg > 0x7fffffff) return PJ_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < pl.total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)ws;
+    const int plain = (prec == PJ_F64) ? P_PLAIN64 : P_PLAIN32;
+
+    // 1. plain projections of A (with C) and B (with D^T): M x rG and W x rG
+    PackArgs pa[2] = {pack_args(b, r, true, transA, M, K, A, lda, plain, w + pl.ahat),
+                      pack_args(b, r, false, transB, W, K, B, ldb, plain, w + pl.bhat)};
+    pa[0].geom = pack_geom(M, K, b->L, r, plain);
+    pa[1].geom = pack_geom(W, K, b->L, r, plain);
+    pa[0].plain_ld = pa[1].plain_ld = pl.rg;
+    if (launch_pack_n(plain, pa, 2, st) != 0) return PJ_ERR_HIP;
+    return run_bwd(b, r, transA, transB, M, W, K, w + pl.ahat, w + pl.bhat, pl, dR, lddr, dA, ldda, dB, lddb, prec,
+                   w, st);
+}
+
+size_t pj_gemm_backward_saved_workspace_bytes(int M, int W, int K, int L, int r, int prec)
+{
+    if (M < 1 || W < 1 || K < 1 || L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return 0;
+    return plan_bwd(M, W, K, L, r, prec, saved_geom(M, W, K, L, r, prec).Gp, false).total;
+}
+
+int proj_gemm_backward_saved(pj_basis b, int r, char transA, char transB, int M, int W, int K, const void* saved,
+                             size_t saved_bytes, const void* dR, int64_t lddr, void* dA, int64_t ldda, void* dB,
+                             int64_t lddb, int prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!saved) return PJ_ERR_ARG;
+    int rc = check_bwd(b, r, transA, transB, M, W, K, dR, lddr, dA, ldda, dB, lddb, prec);
+    if (rc != PJ_OK) return rc;
+    const SavedGeom sg = saved_geom(M, W, K, b->L, r, prec);
+    if (saved_bytes < sg.total) return PJ_ERR_WORKSPACE;
+    const BwdPlan pl = plan_bwd(M, W, K, b->L, r, prec, sg.Gp, false);
+    if (pl.rg > 0x7fffffff) return PJ_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < pl.total) return PJ_ERR_WORKSPACE;
+    if (!b->on_device) return PJ_ERR_HIP;
+    const char* sv = (const char*)saved;
+    return run_bwd(b, r, transA, transB, M, W, K, sv, sv + sg.bhat, pl, dR, lddr, dA, ldda, dB, lddb, prec,
+                   (char*)ws, (hipStream_t)stream);
 }
 
 size_t pj_conv1d_method_workspace_bytes(int64_t W, int N, int L, int r, int method, int prec)

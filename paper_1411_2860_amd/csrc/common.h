@@ -118,10 +118,21 @@ struct PackArgs {
     void* out;         // packed operand
     PackGeom geom;
     int64_t plain_ld = 0;  // row stride of a plain output (P_PLAIN32 / P_PLAIN64)
+    // optional second output of a packed (not plain) pass: the same projected
+    // values before conversion, as a plain matrix keep[p * keep_ld + l * Gp + j]
+    // (FP32, FP64 for P_F64) with the packed geometry's Gp; rows p < P only
+    void* keep = nullptr;
+    int64_t keep_ld = 0;
 };
 int launch_pack(int prec, const PackArgs& a, hipStream_t s);
 // Packs n (1 or 2) operands of the same precision in one launch.
 int launch_pack_n(int prec, const PackArgs* a, int n, hipStream_t s);
+// Fragment-order copy of an operand that is not projected (the contraction
+// index kept in its natural order, zero past K up to the geometry's padded
+// length nkb * KB; rows past P zero): the operands of the backward's
+// contractions over the rows or columns of R.  a.L, a.r and a.coef are
+// unused; a.geom gives the padded shape.  Not for the FP8 formats (-2).
+int launch_repack_n(int prec, const PackArgs* a, int n, hipStream_t s);
 // Packs any number of operands in one launch, driven by a job table that is
 // copied into `table` (device memory of pack_grouped_table_bytes(n) bytes).
 size_t pack_grouped_table_bytes(int n);

@@ -176,8 +176,25 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n)
     return x * q + (x < rem ? x : rem) + i;
 }
 
+// Fragment sets in flight in the direct-load body: enough k-blocks ahead to
+// cover the load latency with the matrix work of the wave's own blocks (a
+// 16-bit k-block is 4x shorter on the matrix cores than an FP32 one).
+template <int PREC, int WM, int WN>
+constexpr int gemm_direct_depth()
+{
+    constexpr int blocks = WM * WN * MT<PREC>::PLANES;
+    if constexpr (PREC == P_FP8X2) return 2;           // 32-byte fragments in two planes
+    if constexpr (PREC == P_F32 || PREC == P_F64) return blocks >= 4 ? 2 : 4;
+    return blocks >= 8 ? 2 : (blocks >= 4 ? 4 : 8);
+}
+
 // One workgroup tile (tm, tn) of R = X Y^T: the body shared by the single
-// and the grouped (persistent) launches.
+// and the grouped (persistent) launches.  Every wave streams its fragments
+// through a ring of DEPTH k-block sets; all loads are unconditional (row
+// blocks past the operand read row block 0: their outputs are never stored,
+// and loads past the end of the contraction read k-block 0 and are never
+// used), so the compiler's wait counts stay exact instead of draining every
+// load at each branch.
 template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 __device__ __forceinline__ void gemm_tile(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
@@ -189,6 +206,7 @@ __device__ __forceinline__ void gemm_tile(
     using frag = typename T::frag;
     using acc_t = typename T::acc;
     constexpr int RB = T::RB, PL = T::PLANES;
+    constexpr int DEPTH = gemm_direct_depth<PREC, WM, WN>();
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -197,17 +215,10 @@ __device__ __forceinline__ void gemm_tile(
     const int64_t cb0 = (tn * WAVES_N + wn) * WN;
 
     int64_t xt[WM], yt[WN];   // first tile index of each row block
-    bool xv[WM], yv[WN];
 #pragma unroll
-    for (int a = 0; a < WM; ++a) {
-        xv[a] = rb0 + a < x_nrb;
-        xt[a] = (xv[a] ? rb0 + a : 0) * x_nkb + kb_lo;   // k-blocks kb_lo .. kb_lo + nkb - 1
-    }
+    for (int a = 0; a < WM; ++a) xt[a] = nkb > 0 ? (rb0 + a < x_nrb ? rb0 + a : 0) * x_nkb + kb_lo : 0;
 #pragma unroll
-    for (int b = 0; b < WN; ++b) {
-        yv[b] = cb0 + b < y_nrb;
-        yt[b] = (yv[b] ? cb0 + b : 0) * y_nkb + kb_lo;
-    }
+    for (int b = 0; b < WN; ++b) yt[b] = nkb > 0 ? (cb0 + b < y_nrb ? cb0 + b : 0) * y_nkb + kb_lo : 0;
 
     acc_t acc[WM][WN];
 #pragma unroll
@@ -217,43 +228,50 @@ __device__ __forceinline__ void gemm_tile(
 #pragma unroll
             for (int j = 0; j < T::NACC; ++j) acc[a][b][j] = 0;
 
-    frag xc[WM][PL], yc[WN][PL];
-    auto load = [&](int64_t kb, frag (&xf)[WM][PL], frag (&yf)[WN][PL]) {
-#pragma unroll
-        for (int a = 0; a < WM; ++a)
-#pragma unroll
-            for (int pl = 0; pl < PL; ++pl)
-                xf[a][pl] = xv[a] ? T::load(X + pl * x_plane, x_pb, xt[a] + kb, lane) : frag{};
-#pragma unroll
-        for (int b = 0; b < WN; ++b)
-#pragma unroll
-            for (int pl = 0; pl < PL; ++pl)
-                yf[b][pl] = yv[b] ? T::load(Y + pl * y_plane, y_pb, yt[b] + kb, lane) : frag{};
-    };
-
     // The contraction runs from the last k-block to the first, i.e. from the
     // highest projection down to l = 0: with an energy-compacting basis the
     // small high-order products are accumulated before the large low-order
-    // ones, which keeps the FP32 running sum accurate.
-    if (nkb > 0) load(nkb - 1, xc, yc);
-    for (int64_t kb = nkb - 1; kb >= 0; --kb) {
-        frag xn[WM][PL], yn[WN][PL];
-        if (kb > 0) load(kb - 1, xn, yn);
+    // ones, which keeps the FP32 running sum accurate.  Step t contracts
+    // k-block nkb - 1 - t with register set t % DEPTH, then loads step
+    // t + DEPTH into it.  The loop runs whole trips of DEPTH steps with no
+    // branch inside (a branch would merge unequal in-flight load counts and
+    // make the compiler drain every load once per trip); the remaining
+    // nkb % DEPTH steps follow it.
+    const int nk = (int)nkb;                      // 32-bit step arithmetic (scalar); nkb < 2^31
+    frag xf[DEPTH][WM][PL], yf[DEPTH][WN][PL];
+    auto load = [&](int t, frag (&xd)[WM][PL], frag (&yd)[WN][PL]) {
+        const int kb = t < nk ? nk - 1 - t : 0;
 #pragma unroll
         for (int a = 0; a < WM; ++a)
 #pragma unroll
-            for (int b = 0; b < WN; ++b) T::mma(acc[a][b], xc[a], yc[b]);
-        if (kb > 0) {
+            for (int pl = 0; pl < PL; ++pl) xd[a][pl] = T::load(X + pl * x_plane, x_pb, xt[a] + kb, lane);
 #pragma unroll
-            for (int a = 0; a < WM; ++a)
+        for (int b = 0; b < WN; ++b)
 #pragma unroll
-                for (int pl = 0; pl < PL; ++pl) xc[a][pl] = xn[a][pl];
+            for (int pl = 0; pl < PL; ++pl) yd[b][pl] = T::load(Y + pl * y_plane, y_pb, yt[b] + kb, lane);
+    };
+    auto mma_set = [&](const frag (&xd)[WM][PL], const frag (&yd)[WN][PL]) {
 #pragma unroll
-            for (int b = 0; b < WN; ++b)
+        for (int a = 0; a < WM; ++a)
 #pragma unroll
-                for (int pl = 0; pl < PL; ++pl) yc[b][pl] = yn[b][pl];
+            for (int b = 0; b < WN; ++b) T::mma(acc[a][b], xd[a], yd[b]);
+    };
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) load(d, xf[d], yf[d]);
+    const int nfull = nk - nk % DEPTH;
+    for (int t0 = 0; t0 < nfull; t0 += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            mma_set(xf[d], yf[d]);
+            load(t0 + d + DEPTH, xf[d], yf[d]);
+            // keep each step's loads where they are: left free, the scheduler
+            // sinks them towards their use and shortens the prefetch distance
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+#pragma unroll
+    for (int d = 0; d + 1 < DEPTH; ++d)
+        if (d < nk - nfull) mma_set(xf[d], yf[d]);
 
 #pragma unroll
     for (int a = 0; a < WM; ++a)
@@ -285,10 +303,12 @@ constexpr int gemm_lds_ks()
 // KS k-blocks the workgroup copies its BMB + BNB packed tiles per k-block
 // (already in fragment order, 1 KiB per plane, so the copy is a plain
 // coalesced 16-byte-per-lane stream) into one of two LDS stages while its
-// waves run the matrix instructions on fragments of the other stage.  Each tile is fetched from L2 once per
-// workgroup instead of once per wave, and the global loads of k-block k+1
-// overlap the MFMAs of k-block k.  16-byte lane formats only (not FP8).
-template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
+// waves run the matrix instructions on fragments of the other stage.  Each
+// tile is fetched from L2 once per workgroup instead of once per wave.  The
+// global loads run DEPTH steps ahead through a ring of register sets, all
+// unconditional (as in gemm_tile) so that each wait covers exactly the set
+// being parked.  16-byte lane formats only (not FP8).
+template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int DEPTH>
 __device__ __forceinline__ void gemm_tile_lds(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
@@ -307,6 +327,7 @@ __device__ __forceinline__ void gemm_tile_lds(
     constexpr int NCH = NCH1 * KS;                 // and per step
     constexpr int PER_T = (NCH + NT - 1) / NT;
     static_assert(sizeof(frag) == 16, "LDS path is for 16-byte lane formats");
+    static_assert(PER_T <= 32, "validity bits of a register set");
     (void)x_pb;
     (void)y_pb;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -318,48 +339,58 @@ __device__ __forceinline__ void gemm_tile_lds(
     const int wm = wave % WAVES_M, wn = wave / WAVES_M;
     const int64_t rbB = tm * BMB, cbB = tn * BNB;
 
-    // source of chunk c of a step: k-block kk[i] = c / NCH1 of the step,
-    // tile ti = (c % NCH1) / 64 = blk * PL + pl
-    const char* src[PER_T];
-    bool ok[PER_T];
+    // chunk c = tid + i NT of a step belongs to the 1 KiB tile slot
+    // u = c / 64 = wave + i NW (the same for the 64 lanes of a wave): k-block
+    // kk = u / NTILE of the step, tile ti = u % NTILE = blk * PL + pl.  The
+    // per-slot source (row block and plane, first k-block of the range) is
+    // wave-uniform; each lane adds its 16 bytes.  Row blocks past the operand
+    // read row block 0 (their outputs are never stored); slots past the step
+    // read tile 0 and are dropped.
+    constexpr int NW = WAVES_M * WAVES_N;
+    const char* srcw[PER_T];
     int kk[PER_T];
 #pragma unroll
     for (int i = 0; i < PER_T; ++i) {
-        const int c = tid + i * NT;
-        kk[i] = c / NCH1;
-        const int ti = (c % NCH1) / 64, lc = c % 64;
+        const int u = wave + i * NW;
+        kk[i] = u / NTILE;
+        const int ti = u % NTILE;
         const int blk = ti / PL, pl = ti % PL;
-        ok[i] = false;
-        src[i] = X;
-        if (c < NCH) {
-            if (blk < BMB) {
-                const int64_t rb = rbB + blk;
-                ok[i] = rb < x_nrb;
-                src[i] = X + pl * x_plane + (((ok[i] ? rb : 0) * x_nkb + kb_lo) * 64 + lc) * 16;
-            } else {
-                const int64_t cb = cbB + blk - BMB;
-                ok[i] = cb < y_nrb;
-                src[i] = Y + pl * y_plane + (((ok[i] ? cb : 0) * y_nkb + kb_lo) * 64 + lc) * 16;
-            }
+        const int64_t base = nkb > 0 ? kb_lo : 0;
+        if (u * 64 >= NCH) {
+            srcw[i] = X;
+        } else if (blk < BMB) {
+            const int64_t rb = rbB + blk;
+            srcw[i] = X + pl * x_plane + ((rb < x_nrb ? rb : 0) * x_nkb + base) * 1024;
+        } else {
+            const int64_t cb = cbB + blk - BMB;
+            srcw[i] = Y + pl * y_plane + ((cb < y_nrb ? cb : 0) * y_nkb + base) * 1024;
         }
     }
-    // two register sets: the loads of step st + 2 are issued while step st is
-    // contracted, so each global load has two k-blocks of work to hide behind
-    f32x4 stage0[PER_T], stage1[PER_T];
-    // loads of step st: k-blocks nkb - 1 - st KS - kk (zeros below k-block 0)
-    auto gload = [&](int64_t st, f32x4 (&stage)[PER_T]) {
+    // loads of step st: k-blocks nkb - 1 - st KS - kk (bit i of `zero` set
+    // where that is below k-block 0: those chunks are parked as zeros; steps
+    // past the end read k-block 0 and are never contracted)
+    f32x4 stg[DEPTH][PER_T];
+    unsigned zero[DEPTH];
+    const int nk = (int)nkb;                      // 32-bit step arithmetic (scalar)
+    const int nst = (nk + KS - 1) / KS;
+    auto gload = [&](int st, f32x4 (&stage)[PER_T], unsigned& z) {
+        z = 0;
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
-            const int64_t kb = nkb - 1 - st * KS - kk[i];
-            stage[i] = ok[i] && kb >= 0 ? *reinterpret_cast<const f32x4*>(src[i] + kb * 1024)
-                                        : f32x4{0.f, 0.f, 0.f, 0.f};
+            const int kb = nk - 1 - st * KS - kk[i];
+            z |= (unsigned)(kb < 0) << i;
+            stage[i] = *reinterpret_cast<const f32x4*>(srcw[i] + (int64_t)(kb < 0 ? 0 : kb) * 1024 + lane * 16);
         }
     };
-    auto swrite = [&](int s, const f32x4 (&stage)[PER_T]) {
+    auto swrite = [&](int s, const f32x4 (&stage)[PER_T], unsigned z) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
             const int c = tid + i * NT;
-            if (c < NCH) lds[s * NCH + c] = stage[i];
+            // zeroing by a mask (not a select, which the compiler may turn
+            // into a branch per chunk)
+            const int m = (z >> i) & 1 ? 0 : -1;
+            if ((i + 1) * NT <= NCH || c < NCH)
+                lds[s * NCH + c] = __builtin_bit_cast(f32x4, __builtin_bit_cast(i32x4, stage[i]) & m);
         }
     };
 
@@ -395,25 +426,36 @@ __device__ __forceinline__ void gemm_tile_lds(
                 for (int b = 0; b < WN; ++b) T::mma(acc[a][b], fa[a], fb[b]);
         }
     };
-    // step st (LDS buffer st & 1): issue the loads of step st + 2 into the
-    // register set that held step st, contract, then park step st + 1 (the
-    // other register set) in the other LDS buffer
-    const int64_t nst = (nkb + KS - 1) / KS;
-    auto step = [&](int64_t st, f32x4 (&ld_set)[PER_T], const f32x4 (&st_set)[PER_T]) {
-        if (st + 2 < nst) gload(st + 2, ld_set);
-        contract((int)(st & 1));
-        if (st + 1 < nst) swrite((int)((st + 1) & 1), st_set);
-        __syncthreads();
-    };
-    if (nst > 0) {
-        gload(0, stage0);
-        swrite(0, stage0);
-    }
-    if (nst > 1) gload(1, stage1);
+    // step t (LDS buffer t & 1): issue the loads of step t + DEPTH into the
+    // register set that held step t (parked in LDS during step t - 1),
+    // contract, then park step t + 1 in the other LDS buffer.  As in
+    // gemm_tile, whole trips of DEPTH steps run without a branch (DEPTH is
+    // even, so the buffer of step t0 + d is d & 1; the last trip may park a
+    // step past the end, which nothing reads), then the remaining nst % DEPTH
+    // steps.
+    static_assert(DEPTH % 2 == 0, "LDS buffer parity per trip position");
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) gload(d, stg[d], zero[d]);
+    if (nst > 0) swrite(0, stg[0], zero[0]);
     __syncthreads();
-    for (int64_t st = 0; st < nst; st += 2) {
-        step(st, stage0, stage1);
-        if (st + 1 < nst) step(st + 1, stage1, stage0);
+    const int nfull = nst - nst % DEPTH;
+    for (int t0 = 0; t0 < nfull; t0 += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            gload(t0 + d + DEPTH, stg[d], zero[d]);
+            __builtin_amdgcn_sched_barrier(0);     // the loads go out before the step's matrix work
+            contract(d & 1);
+            swrite((d + 1) & 1, stg[(d + 1) % DEPTH], zero[(d + 1) % DEPTH]);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int d = 0; d + 1 < DEPTH; ++d) {
+        if (d < nst - nfull) {
+            contract(d & 1);
+            if (d + 1 < nst - nfull) swrite((d + 1) & 1, stg[d + 1], zero[d + 1]);
+            __syncthreads();
+        }
     }
 
     const int64_t rb0 = rbB + wm * WM, cb0 = cbB + wn * WN;
@@ -435,7 +477,8 @@ __device__ __forceinline__ void gemm_tile_lds(
             }
 }
 
-// Kernel body selector: KIND 0 = direct fragment loads, 1 = LDS-staged.
+// Kernel body selector: KIND 0 = direct fragment loads, 1 = LDS-staged with
+// loads two steps ahead, 2 = LDS-staged with loads four steps ahead.
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 __device__ __forceinline__ void gemm_any(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
@@ -443,8 +486,8 @@ __device__ __forceinline__ void gemm_any(
     int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
     float beta, int64_t tm, int64_t tn)
 {
-    if constexpr (KIND == 1 && sizeof(typename MT<PREC>::frag) == 16)
-        gemm_tile_lds<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
+    if constexpr (KIND >= 1 && sizeof(typename MT<PREC>::frag) == 16)
+        gemm_tile_lds<PREC, WM, WN, WAVES_M, WAVES_N, KIND == 2 ? 4 : 2>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
                                                       nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
     else
         gemm_tile<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
@@ -454,7 +497,7 @@ __device__ __forceinline__ void gemm_any(
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 constexpr size_t gemm_lds_bytes()
 {
-    if constexpr (KIND == 1 && sizeof(typename MT<PREC>::frag) == 16)
+    if constexpr (KIND >= 1 && sizeof(typename MT<PREC>::frag) == 16)
         return 2ull * gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>() * (WM * WAVES_M + WN * WAVES_N) *
                MT<PREC>::PLANES * 1024;
     return 0;
@@ -545,7 +588,7 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
 
 }  // namespace
 
-// Tile configurations: (kind: 0 direct fragment loads, 1 LDS-staged; MFMA
+// Tile configurations: (kind: 0 direct fragment loads, 1 / 2 LDS-staged; MFMA
 // blocks per wave along M, along N; waves along M, along N; minimum resident
 // workgroups per CU).  The workgroup tile is RB*WM*WAVES_M x RB*WN*WAVES_N.
 // FP8 runs the LDS kinds as direct.
@@ -560,7 +603,12 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     X(7, 1, 2, 4, 2, 2, 1)   \
     X(8, 1, 4, 2, 2, 2, 1)   \
     X(9, 1, 2, 2, 2, 4, 1)   \
-    X(10, 1, 2, 2, 4, 2, 1)
+    X(10, 1, 2, 2, 4, 2, 1)  \
+    X(11, 2, 2, 2, 2, 2, 2)  \
+    X(12, 2, 2, 4, 2, 2, 1)  \
+    X(13, 2, 4, 2, 2, 2, 1)  \
+    X(14, 2, 4, 4, 2, 2, 1)  \
+    X(15, 2, 2, 2, 4, 2, 1)
 
 namespace {
 struct TileCfg { int wm, wn, wavm, wavn; };
@@ -636,15 +684,24 @@ int gemm_config_tile(int prec, int cfg, int* tile_m, int* tile_n)
 
 int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
 {
-    (void)nkb;
     // small problems: smaller tiles so that the grid still covers the chip
     const int64_t tiles128 = cdiv(P, 128) * cdiv(Q, 128);
     if (tiles128 < 256) return 5;
-    if (prec == P_F64) return 10;                                  // LDS, 8 waves, 128 x 64 (16 x 16 blocks)
-    if (prec == P_FP8) return 0;
-    if (prec == P_FP8X2) return 5;
-    if (prec == P_BF16X3 || prec == P_F16X3 || prec == P_F32) return 10;   // LDS 256 x 128, 8 waves
-    return 6;                                                      // LDS 128 x 128
+    // (measured on the recognition and backward shapes, one timing per config)
+    const bool fill256 = cdiv(P, 256) * cdiv(Q, 128) >= 256;   // 256 x 128 tiles still cover the chip
+    switch (prec) {
+    case P_F64: return 10;                                 // LDS, 8 waves, 128 x 64 (16 x 16 blocks)
+    case P_F32: return 10;                                 // LDS 256 x 128, 8 waves
+    case P_FP8:
+    case P_FP8X2: return 9;                                // 128 x 256, 8 waves, fragments direct
+    case P_BF16X3:
+    case P_F16X3:
+        if (!fill256) return 0;
+        return nkb >= 128 ? 2 : 9;                         // long: direct 128 x 256; else LDS 8 waves
+    default:                                               // BF16, FP16
+        if (!fill256) return 0;                            // direct 128 x 128
+        return nkb >= 128 ? 15 : 9;                        // long: loads four steps ahead
+    }
 }
 
 // Contiguous k-block ranges for a contraction whose tile grid alone would

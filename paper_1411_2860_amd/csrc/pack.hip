@@ -67,6 +67,8 @@ struct PackJob {
     // jj, t) at (jj * TCp + t) * RT + rr, filled by single-value direct loads
     // along the contiguous rows of the source.
     int tdma, RT;
+    TIn* keep;          // plain copy of the projections (nullptr: none)
+    int64_t keep_ld;
 };
 
 // ---- OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits,
@@ -684,6 +686,14 @@ __device__ __forceinline__ void pack_tile(const PackJob<TIn>& J, int64_t tix)
                         for (int e = 0; e < Ec; ++e) dst[e] = acc[c][q][e];
                     }
                 } else {
+                    if (J.keep) {
+                        const int64_t p = p0 + row;
+                        if (p < J.P) {
+                            TIn* dst = J.keep + p * J.keep_ld + (int64_t)l * J.Gp + j0 + g * Ec;
+#pragma unroll
+                            for (int e = 0; e < Ec; ++e) dst[e] = acc[c][q][e];
+                        }
+                    }
                     const int64_t kbi = ((int64_t)l * J.Gp + j0) / KB;
                     const int64_t tile = rbi * J.nkb + kbi;
                     if constexpr (PREC == P_FP8 || PREC == P_FP8X2) {
@@ -766,6 +776,8 @@ PackJob<TIn> make_job(const PackArgs& a)
     j.plane_stride = g.plane_bytes + g.scale_plane;
     j.plane_bytes = g.plane_bytes;
     j.plain_ld = a.plain_ld;
+    j.keep = (TIn*)a.keep;
+    j.keep_ld = a.keep_ld;
     j.nrb = g.nrb;
     j.ngt = g.Gp / ly.KB;
     // whole row blocks, so that padding rows are written (as zeros) too
@@ -959,7 +971,114 @@ int launch_grouped_p(const PackArgs* a, int n, void* table, hipStream_t s)
     }
 }
 
+// ---- unprojected operands ----------------------------------------------------
+// A workgroup copies a kRpRows x kRpK block of the source (rows p, natural
+// contraction index k) into LDS with coalesced loads along whichever index
+// is contiguous in memory, then writes the block's packed tiles, one 16-byte
+// lane vector per lane slot, converted as the format's packer does.
+constexpr int kRpRows = 64, kRpK = 64;
+
+template <typename TIn>
+struct RepackJob {
+    const TIn* X; int64_t ld; int trans;
+    int64_t P, K;
+    char* out;
+    int64_t nrb, nkb, plane_stride;
+    int64_t ntk, nblk;            // k blocks of the workgroup grid, workgroups
+};
+
+template <typename TIn, int PREC>
+__device__ __forceinline__ void repack_block(const RepackJob<TIn>& J, int64_t b)
+{
+    constexpr Layout ly = layout_of(PREC);
+    constexpr int RB = ly.RB, KB = ly.KB, E = ly.E;
+    __shared__ TIn sm[kRpRows][kRpK + 1];
+    const int64_t p0 = (b / J.ntk) * kRpRows, k0 = (b % J.ntk) * kRpK;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // 64 consecutive elements of the contiguous index per wave instruction
+#pragma unroll 4
+    for (int q = wave; q < kRpRows; q += kPackThreads / 64) {
+        int rr, kk;
+        if (J.trans) { kk = q; rr = lane; }      // source row k0 + q, elements p0 .. p0 + 63
+        else { rr = q; kk = lane; }              // source row p0 + q, elements k0 .. k0 + 63
+        const int64_t p = p0 + rr, k = k0 + kk;
+        TIn v = (TIn)0;
+        if (p < J.P && k < J.K) v = J.trans ? J.X[k * J.ld + p] : J.X[p * J.ld + k];
+        sm[rr][kk] = v;
+    }
+    __syncthreads();
+    constexpr int NTB = (kRpRows / RB) * (kRpK / KB);     // tiles of the block
+#pragma unroll
+    for (int s0 = 0; s0 < NTB * 64; s0 += kPackThreads) {
+        const int s = s0 + tid;
+        const int q = s / 64, ln = s % 64;
+        const int rbl = q / (kRpK / KB), kbl = q % (kRpK / KB);
+        const int64_t rb = p0 / RB + rbl, kb = k0 / KB + kbl;
+        if (rb < J.nrb && kb < J.nkb) {
+            const int g = ln / RB, rib = ln % RB;
+            TIn v[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = sm[rbl * RB + rib][kbl * KB + g * E + e];
+            store_lane<PREC, E, TIn>(J.out, ((rb * J.nkb + kb) * 64 + ln) * (int64_t)ly.LB, J.plane_stride, 0, v);
+        }
+    }
+    (void)lane;
+}
+
+template <typename TIn, int PREC>
+__global__ __launch_bounds__(kPackThreads) void repack_kernel(RepackJob<TIn> ja, RepackJob<TIn> jb)
+{
+    const int64_t b = blockIdx.x;
+    if (b < ja.nblk) repack_block<TIn, PREC>(ja, b);
+    else repack_block<TIn, PREC>(jb, b - ja.nblk);
+}
+
+template <typename TIn, int PREC>
+RepackJob<TIn> make_repack(const PackArgs& a)
+{
+    constexpr Layout ly = layout_of(PREC);
+    RepackJob<TIn> j;
+    j.X = (const TIn*)a.X;
+    j.ld = a.ld;
+    j.trans = a.trans;
+    j.P = a.P;
+    j.K = a.K;
+    j.out = (char*)a.out;
+    j.nrb = a.geom.nrb;
+    j.nkb = a.geom.nkb;
+    j.plane_stride = a.geom.plane_bytes + a.geom.scale_plane;
+    j.ntk = cdiv(j.nkb * ly.KB, kRpK);
+    j.nblk = cdiv(j.nrb * ly.RB, kRpRows) * j.ntk;
+    return j;
+}
+
+template <typename TIn, int PREC>
+int launch_repack_t(const PackArgs* a, int n, hipStream_t s)
+{
+    const RepackJob<TIn> ja = make_repack<TIn, PREC>(a[0]);
+    RepackJob<TIn> jb = n > 1 ? make_repack<TIn, PREC>(a[1]) : ja;
+    if (n < 2) jb.nblk = 0;
+    const int64_t grid = ja.nblk + jb.nblk;
+    if (grid > 0x7fffffff) return -2;
+    if (grid == 0) return 0;
+    hipLaunchKernelGGL((repack_kernel<TIn, PREC>), dim3((unsigned)grid), dim3(kPackThreads), 0, s, ja, jb);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 }  // namespace
+
+int launch_repack_n(int prec, const PackArgs* a, int n, hipStream_t s)
+{
+    switch (prec) {
+    case P_F64:    return launch_repack_t<double, P_F64>(a, n, s);
+    case P_F32:    return launch_repack_t<float, P_F32>(a, n, s);
+    case P_BF16:   return launch_repack_t<float, P_BF16>(a, n, s);
+    case P_BF16X3: return launch_repack_t<float, P_BF16X3>(a, n, s);
+    case P_F16:    return launch_repack_t<float, P_F16>(a, n, s);
+    case P_F16X3:  return launch_repack_t<float, P_F16X3>(a, n, s);
+    default:       return -2;
+    }
+}
 
 int launch_pack_n(int prec, const PackArgs* a, int n, hipStream_t s)
 {

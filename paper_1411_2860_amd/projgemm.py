@@ -17,7 +17,8 @@ __all__ = [
     "ProjGemmError", "lib", "lib_path", "Basis", "PREC", "BASIS",
     "gemm", "gemm_noalloc", "pack_a", "pack_b", "pack_ab", "tile_configs", "gemm_packed", "packed_bytes", "gemm_workspace_bytes",
     "conv1d", "conv1d_workspace_bytes", "conv1d_fft", "conv1d_fft_workspace_bytes", "conv1d_method",
-    "conv1d_method_workspace_bytes", "gemm_backward", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
+    "conv1d_method_workspace_bytes", "gemm_backward", "gemm_save", "gemm_saved_bytes",
+    "gemm_backward_saved", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
     "status_str",
 ]
 
@@ -72,6 +73,12 @@ _SIGNATURES = {
     "pj_gemm_backward_workspace_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
     "proj_gemm_backward": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                                 _i64, _i, _vp, _sz, _vp]),
+    "pj_gemm_saved_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
+    "proj_gemm_save": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _f, _vp, _i64, _i, _vp, _sz, _vp,
+                            _sz, _vp]),
+    "pj_gemm_backward_saved_workspace_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
+    "proj_gemm_backward_saved": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _sz, _vp, _i64, _vp, _i64, _vp, _i64, _i,
+                                      _vp, _sz, _vp]),
     "proj_conv1d": (_i, [_vp, _i, _i, _i64, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp]),
     "pj_conv1d_rate_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i, _i]),
     "pj_conv1d_circular_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i]),
@@ -524,4 +531,60 @@ def gemm_backward(A, B, dR, r: int, basis: Basis, prec="f32", transA=False, tran
                                     _ptr(dA) if dA is not None else None, dA.stride(0) if dA is not None else 1,
                                     _ptr(dB) if dB is not None else None, dB.stride(0) if dB is not None else 1,
                                     p, _ptr(workspace), workspace.numel(), _stream(stream)), "proj_gemm_backward")
+    return dA, dB
+
+
+def gemm_saved_bytes(M: int, W: int, K: int, L: int, r: int, prec="f32") -> int:
+    return int(lib().pj_gemm_saved_bytes(M, W, K, L, r, _prec(prec)))
+
+
+def gemm_save(A, B, r: int, basis: Basis, prec="f32", transA=False, transB=False, out=None, workspace=None,
+              saved=None, stream=None):
+    """(R, saved): gemm() that also keeps the plain projections of A and B
+    (a byte tensor) for gemm_backward_saved."""
+    import torch
+    p = _prec(prec)
+    M, K = (A.shape[1], A.shape[0]) if transA else tuple(A.shape)
+    K2, W = (B.shape[1], B.shape[0]) if transB else tuple(B.shape)
+    if K2 != K:
+        raise ValueError(f"contraction mismatch {K} vs {K2}")
+    dt = torch.float64 if p == PREC["f64"] else torch.float32
+    if A.dtype != dt or B.dtype != dt:
+        raise TypeError(f"A and B must be {dt}")
+    if A.stride(1) != 1 or B.stride(1) != 1:
+        raise ValueError("A and B need unit stride along their last dimension")
+    if out is None:
+        out = torch.empty((M, W), dtype=dt, device=A.device)
+    if workspace is None:
+        workspace = _byte_buffer(gemm_workspace_bytes(M, W, K, basis.L, r, p), A.device)
+    if saved is None:
+        saved = _byte_buffer(gemm_saved_bytes(M, W, K, basis.L, r, p), A.device)
+    _check(lib().proj_gemm_save(basis.handle, r, b"T" if transA else b"N", b"T" if transB else b"N", M, W, K,
+                                _ptr(A), A.stride(0), _ptr(B), B.stride(0), 0.0, _ptr(out), out.stride(0), p,
+                                _ptr(workspace), workspace.numel(), _ptr(saved), saved.numel(), _stream(stream)),
+           "proj_gemm_save")
+    return out, saved
+
+
+def gemm_backward_saved(saved, dR, r: int, basis: Basis, M: int, W: int, K: int, prec="f32", transA=False,
+                        transB=False, need_dA=True, need_dB=True, dtype=None, workspace=None, stream=None):
+    """(dA, dB) from the projections gemm_save kept; dA has the layout of A
+    (M x K, K x M if transA), dB that of B (K x W, W x K if transB)."""
+    import torch
+    p = _prec(prec)
+    dt = dtype or (torch.float64 if p == PREC["f64"] else torch.float32)
+    dev = dR.device
+    dA = torch.empty((K, M) if transA else (M, K), dtype=dt, device=dev) if need_dA else None
+    dB = torch.empty((W, K) if transB else (K, W), dtype=dt, device=dev) if need_dB else None
+    if dR.stride(1) != 1:
+        dR = dR.contiguous()
+    need = int(lib().pj_gemm_backward_saved_workspace_bytes(M, W, K, basis.L, r, p))
+    if workspace is None:
+        workspace = _byte_buffer(need, dev)
+    _check(lib().proj_gemm_backward_saved(basis.handle, r, b"T" if transA else b"N", b"T" if transB else b"N", M, W,
+                                          K, _ptr(saved), saved.numel(), _ptr(dR), dR.stride(0),
+                                          _ptr(dA) if dA is not None else None, dA.stride(0) if dA is not None else 1,
+                                          _ptr(dB) if dB is not None else None, dB.stride(0) if dB is not None else 1,
+                                          p, _ptr(workspace), workspace.numel(), _stream(stream)),
+           "proj_gemm_backward_saved")
     return dA, dB

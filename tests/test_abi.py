@@ -49,7 +49,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_tile_configs(lib):
     cfgs = pg.tile_configs("f32")
-    assert len(cfgs) == 11 and (128, 128) in cfgs
+    assert len(cfgs) == 16 and (128, 128) in cfgs
     assert all(m % 32 == 0 and n % 32 == 0 for m, n in cfgs)
     assert all(m % 16 == 0 for m, _ in pg.tile_configs("f64"))
 
@@ -152,6 +152,49 @@ def test_valid_call_without_device_reports_hip(lib, basis16):
     if torch.cuda.is_available():
         pytest.skip("a device is present")
     assert _gemm(lib, basis16) == HIP
+
+
+def test_saved_forward_backward_validation(lib, basis16):
+    """proj_gemm_save / proj_gemm_backward_saved: the kept projections' size
+    (A_hat then B_hat, 256-byte aligned, Gp rounded to the k-block) and the
+    argument errors, before any device work."""
+    b = basis16
+    # f32: K = 150, L = 16 -> G = 10, Gp = 16 (k-blocks of 8); bf16 the same (16)
+    a256 = lambda n: -(-n // 256) * 256
+    assert pg.gemm_saved_bytes(45, 33, 150, 16, 5, "f32") == a256(45 * 5 * 16 * 4) + a256(33 * 5 * 16 * 4)
+    assert pg.gemm_saved_bytes(45, 33, 150, 16, 5, "f64") == a256(45 * 5 * 16 * 8) + a256(33 * 5 * 16 * 8)
+    # 16-bit formats round the groups to 16, FP8 to 64
+    assert pg.gemm_saved_bytes(45, 33, 150, 16, 5, "bf16") == a256(45 * 5 * 16 * 4) + a256(33 * 5 * 16 * 4)
+    assert pg.gemm_saved_bytes(45, 33, 400, 16, 5, "bf16") == a256(45 * 5 * 32 * 4) + a256(33 * 5 * 32 * 4)
+    assert pg.gemm_saved_bytes(45, 33, 400, 16, 5, "fp8") == a256(45 * 5 * 64 * 4) + a256(33 * 5 * 64 * 4)
+    assert pg.gemm_saved_bytes(45, 33, 150, 16, 17, "f32") == 0
+    sv = pg.gemm_saved_bytes(8, 8, 32, 16, 4, "f32")
+
+    def save(r=4, saved=FAKE, saved_bytes=sv, lda=32, ws_bytes=1 << 30):
+        return lib.proj_gemm_save(b.handle, r, b"N", b"N", 8, 8, 32, FAKE, lda, FAKE, 8, 0.0, FAKE, 8, 1, FAKE,
+                                  ws_bytes, saved, saved_bytes, None)
+
+    assert save(r=17) == ARG
+    assert save(saved=None) == ARG
+    assert save(lda=31) == SHAPE
+    assert save(saved_bytes=sv - 1) == WS
+    assert save(ws_bytes=16) == WS
+    wb = lib.pj_gemm_backward_saved_workspace_bytes(8, 8, 32, 16, 4, 1)
+    assert wb > 0
+
+    def bwd(r=4, saved=FAKE, saved_bytes=sv, dA=FAKE, dB=FAKE, lddr=8, ws_bytes=wb):
+        return lib.proj_gemm_backward_saved(b.handle, r, b"N", b"N", 8, 8, 32, saved, saved_bytes, FAKE, lddr,
+                                            dA, 32, dB, 8, 1, FAKE, ws_bytes, None)
+
+    assert bwd(saved=None) == ARG
+    assert bwd(dA=None, dB=None) == ARG
+    assert bwd(r=0) == ARG
+    assert bwd(lddr=7) == SHAPE
+    assert bwd(saved_bytes=sv - 1) == WS
+    assert bwd(ws_bytes=wb - 1) == WS
+    import torch
+    if not torch.cuda.is_available():
+        assert save() == HIP and bwd() == HIP
 
 
 def test_noalloc_validation_and_scratch_limit(lib, basis16):

@@ -63,6 +63,60 @@ def test_backward_parity(pg, prec, transA, transB):
         _tol.assert_within(gB, rB, bB, f"dB {prec} r={r}")
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("transA,transB", [(False, False), (True, True), (False, True)])
+def test_saved_forward_and_backward(pg, prec, transA, transB):
+    """proj_gemm_save: R identical to proj_gemm's, kept projections equal to
+    the oracle's A_c and B_d (paper Sec. III-B) within the projection bound;
+    proj_gemm_backward_saved within the gradient bound of the oracle's.  The
+    library's DCT-II is the orthonormal one, so the kept projections are the
+    oracle's with the columns of eq. (7)'s basis scaled to unit length (and
+    the rows of D = C^-1 scaled inversely); the product is the same."""
+    rng = np.random.default_rng(53)
+    M, K, W, L = 45, 150, 33, 16
+    A, B, dR = rng.standard_normal((M, K)), rng.standard_normal((K, W)), rng.standard_normal((M, W))
+    basis = pg.Basis("dct2", L)
+    C, D = _ref.oracle_basis("dct2", L)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Ad, Bd = _dev(A.T if transA else A, dt), _dev(B.T if transB else B, dt)
+    G = -(-K // L)
+    kb = 8 if prec in ("f64", "f32") else 16
+    Gp = -(-G // kb) * kb
+    u_acc = _tol.PREC_UNITS["f64" if prec == "f64" else "f32"][0]
+    for r in (1, 5, 16):
+        R, saved = pg.gemm_save(Ad, Bd, r, basis, prec=prec, transA=transA, transB=transB)
+        R0 = pg.gemm(Ad, Bd, r, basis, prec=prec, transA=transA, transB=transB)
+        torch.cuda.synchronize()
+        assert torch.equal(R, R0), f"{prec} r={r}: saved forward differs from proj_gemm"
+        assert saved.numel() == pg.gemm_saved_bytes(M, W, K, L, r, prec)
+        esz = 8 if prec == "f64" else 4
+        nbh = -(-(M * r * Gp * esz) // 256) * 256
+        flat = saved.cpu().numpy()
+        npdt = np.float64 if prec == "f64" else np.float32
+        ah = flat[:M * r * Gp * esz].view(npdt).reshape(M, r, Gp).astype(np.float64)
+        bh = flat[nbh:nbh + W * r * Gp * esz].view(npdt).reshape(W, r, Gp).astype(np.float64)
+        nrm = np.linalg.norm(C, axis=0)
+        Cn, Dn = C / nrm, D * nrm[:, None]
+        pa = oracle.project_a(A, Cn, r)                    # r x M x G
+        pb = oracle.project_b(B, Dn, r)                    # r x G x W
+        ba = 4.0 * L * u_acc * oracle.project_a(np.abs(A), np.abs(Cn), r) + 1e-300
+        bb = 4.0 * L * u_acc * oracle.project_b(np.abs(B), np.abs(Dn), r) + 1e-300
+        _tol.assert_within(ah[:, :, :G], pa.transpose(1, 0, 2), ba.transpose(1, 0, 2), f"A_hat {prec} r={r}")
+        _tol.assert_within(bh[:, :, :G], pb.transpose(2, 0, 1), bb.transpose(2, 0, 1), f"B_hat {prec} r={r}")
+        assert not ah[:, :, G:].any() and not bh[:, :, G:].any(), "padded groups must be zero"
+        dA, dB = pg.gemm_backward_saved(saved, _dev(dR, dt), r, basis, M, W, K, prec=prec, transA=transA,
+                                        transB=transB)
+        torch.cuda.synchronize()
+        gA = dA.double().cpu().numpy()
+        gB = dB.double().cpu().numpy()
+        gA = gA.T if transA else gA
+        gB = gB.T if transB else gB
+        rA, rB = oracle.gemm_proj_grad(A, B, C, D, r, dR)
+        bA, bB = _grad_bounds(A, B, C, D, r, dR, prec, L)
+        _tol.assert_within(gA, rA, bA, f"saved dA {prec} r={r}")
+        _tol.assert_within(gB, rB, bB, f"saved dB {prec} r={r}")
+
+
 def test_gradcheck_f64(pg):
     """Finite differences of the library's own FP64 forward against its
     backward (torch.autograd.gradcheck)."""
