@@ -188,6 +188,34 @@ constexpr int gemm_direct_depth()
     return blocks >= 8 ? 2 : (blocks >= 4 ? 4 : 8);
 }
 
+// Writes a wave's WM x WN accumulator blocks (block rows from rb0, block
+// columns from cb0) into R, + beta R, inside P x Q.  (Non-temporal stores
+// were measured slower here.)
+template <int PREC, int WM, int WN>
+__device__ __forceinline__ void store_tile(const typename MT<PREC>::acc (&acc)[WM][WN], int lane, int64_t rb0,
+                                           int64_t cb0, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R,
+                                           int64_t ldr, float beta)
+{
+    using T = MT<PREC>;
+    constexpr int RB = T::RB;
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+#pragma unroll
+            for (int j = 0; j < T::NACC; ++j) {
+                int row, col;
+                acc_pos<RB>(j, lane, row, col);
+                const int64_t p = (rb0 + a) * RB + row;
+                const int64_t q = (cb0 + b) * RB + col;
+                if (p < P && q < Q) {
+                    typename T::out_t v = (typename T::out_t)acc[a][b][j];
+                    if (beta != 0.0f) v += (typename T::out_t)beta * R[p * ldr + q];
+                    R[p * ldr + q] = v;
+                }
+            }
+}
+
 // One workgroup tile (tm, tn) of R = X Y^T: the body shared by the single
 // and the grouped (persistent) launches.  Every wave streams its fragments
 // through a ring of DEPTH k-block sets; all loads are unconditional (row
@@ -205,7 +233,7 @@ __device__ __forceinline__ void gemm_tile(
     using T = MT<PREC>;
     using frag = typename T::frag;
     using acc_t = typename T::acc;
-    constexpr int RB = T::RB, PL = T::PLANES;
+    constexpr int PL = T::PLANES;
     constexpr int DEPTH = gemm_direct_depth<PREC, WM, WN>();
 
     const int lane = threadIdx.x & 63;
@@ -273,22 +301,7 @@ __device__ __forceinline__ void gemm_tile(
     for (int d = 0; d + 1 < DEPTH; ++d)
         if (d < nk - nfull) mma_set(xf[d], yf[d]);
 
-#pragma unroll
-    for (int a = 0; a < WM; ++a)
-#pragma unroll
-        for (int b = 0; b < WN; ++b)
-#pragma unroll
-            for (int j = 0; j < T::NACC; ++j) {
-                int row, col;
-                acc_pos<RB>(j, lane, row, col);
-                const int64_t p = (rb0 + a) * RB + row;
-                const int64_t q = (cb0 + b) * RB + col;
-                if (p < P && q < Q) {
-                    typename T::out_t v = (typename T::out_t)acc[a][b][j];
-                    if (beta != 0.0f) v += (typename T::out_t)beta * R[p * ldr + q];
-                    R[p * ldr + q] = v;
-                }
-            }
+    store_tile<PREC, WM, WN>(acc, lane, rb0, cb0, P, Q, R, ldr, beta);
 }
 
 // k-blocks staged per step of the LDS-staged tile: two where both stages
@@ -318,7 +331,7 @@ __device__ __forceinline__ void gemm_tile_lds(
     using T = MT<PREC>;
     using frag = typename T::frag;
     using acc_t = typename T::acc;
-    constexpr int RB = T::RB, PL = T::PLANES;
+    constexpr int PL = T::PLANES;
     constexpr int NT = 64 * WAVES_M * WAVES_N;
     constexpr int BMB = WM * WAVES_M, BNB = WN * WAVES_N;
     constexpr int NTILE = (BMB + BNB) * PL;        // 1 KiB tiles per k-block
@@ -459,26 +472,146 @@ __device__ __forceinline__ void gemm_tile_lds(
     }
 
     const int64_t rb0 = rbB + wm * WM, cb0 = cbB + wn * WN;
+    store_tile<PREC, WM, WN>(acc, lane, rb0, cb0, P, Q, R, ldr, beta);
+}
+
+// The LDS-staged tile with the copies done by the memory pipeline itself:
+// each wave instruction moves one 1 KiB packed tile from global memory
+// straight into a slot of the LDS ring (no registers, no LDS store
+// instructions).  NS stages of KS k-blocks; the copies of step t + NS - 1 are
+// issued at step t, so each has NS - 2 steps of matrix work to land behind.
+// A wave waits for its own copies of the step by count, then the barrier
+// makes every wave's copies visible.  Copies past the end read k-block 0 of
+// their tile and are never contracted; slots below k-block 0 (the last step of
+// a contraction that is not a multiple of KS) are overwritten with zeros once
+// their copy has landed.
+template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int NS>
+__device__ __forceinline__ void gemm_tile_dma(
+    const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
+    const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane, int64_t y_pb,
+    int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
+    float beta, int64_t tm, int64_t tn)
+{
+    using T = MT<PREC>;
+    using frag = typename T::frag;
+    using acc_t = typename T::acc;
+    constexpr int PL = T::PLANES;
+    constexpr int NW = WAVES_M * WAVES_N;
+    constexpr int BMB = WM * WAVES_M, BNB = WN * WAVES_N;
+    constexpr int NTILE = (BMB + BNB) * PL;        // 1 KiB tiles per k-block
+    constexpr int KS = gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>();
+    constexpr int NSLOT = NTILE * KS;              // tiles per step
+    constexpr int PER_W = (NSLOT + NW - 1) / NW;   // copies per wave per step
+    constexpr int NCH = NSLOT * 64;                // 16-byte chunks per stage
+    static_assert(sizeof(frag) == 16, "LDS path is for 16-byte lane formats");
+    static_assert(NSLOT % NW == 0, "every wave issues the same number of copies");
+    (void)x_pb;
+    (void)y_pb;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    f32x4* lds = reinterpret_cast<f32x4*>(smem_raw);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+    const int64_t rbB = tm * BMB, cbB = tn * BNB;
+    const char* srcw[PER_W];
+    int kk[PER_W], slot[PER_W];
+#pragma unroll
+    for (int i = 0; i < PER_W; ++i) {
+        const int u = wave + i * NW;
+        slot[i] = u;
+        kk[i] = u / NTILE;
+        const int ti = u % NTILE;
+        const int blk = ti / PL, pl = ti % PL;
+        const int64_t base = nkb > 0 ? kb_lo : 0;
+        if (blk < BMB) {
+            const int64_t rb = rbB + blk;
+            srcw[i] = X + pl * x_plane + ((rb < x_nrb ? rb : 0) * x_nkb + base) * 1024;
+        } else {
+            const int64_t cb = cbB + blk - BMB;
+            srcw[i] = Y + pl * y_plane + ((cb < y_nrb ? cb : 0) * y_nkb + base) * 1024;
+        }
+    }
+    const int nk = (int)nkb;
+    const int nst = (nk + KS - 1) / KS;
+    auto copy = [&](int st, int stage) {
+#pragma unroll
+        for (int i = 0; i < PER_W; ++i) {
+            const int kb = nk - 1 - st * KS - kk[i];
+            const char* src = srcw[i] + (int64_t)(kb < 0 ? 0 : kb) * 1024 + lane * 16;
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                             reinterpret_cast<void*>(lds + stage * NCH + slot[i] * 64), 16, 0, 0);
+        }
+    };
+    // after the copies of step st have landed: zero the slots below k-block 0
+    auto fix = [&](int st, int stage) {
+#pragma unroll
+        for (int i = 0; i < PER_W; ++i)
+            if (nk - 1 - st * KS - kk[i] < 0) lds[stage * NCH + slot[i] * 64 + lane] = f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+
+    acc_t acc[WM][WN];
 #pragma unroll
     for (int a = 0; a < WM; ++a)
 #pragma unroll
         for (int b = 0; b < WN; ++b)
 #pragma unroll
-            for (int j = 0; j < T::NACC; ++j) {
-                int row, col;
-                acc_pos<RB>(j, lane, row, col);
-                const int64_t p = (rb0 + a) * RB + row;
-                const int64_t q = (cb0 + b) * RB + col;
-                if (p < P && q < Q) {
-                    typename T::out_t v = (typename T::out_t)acc[a][b][j];
-                    if (beta != 0.0f) v += (typename T::out_t)beta * R[p * ldr + q];
-                    R[p * ldr + q] = v;
-                }
-            }
+            for (int j = 0; j < T::NACC; ++j) acc[a][b][j] = 0;
+    auto contract = [&](int s) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            frag fa[WM][PL], fb[WN][PL];
+            const f32x4* base = lds + s * NCH + k * NTILE * 64;
+#pragma unroll
+            for (int a = 0; a < WM; ++a)
+#pragma unroll
+                for (int pl = 0; pl < PL; ++pl)
+                    fa[a][pl] = *reinterpret_cast<const frag*>(&base[((wm * WM + a) * PL + pl) * 64 + lane]);
+#pragma unroll
+            for (int b = 0; b < WN; ++b)
+#pragma unroll
+                for (int pl = 0; pl < PL; ++pl)
+                    fb[b][pl] = *reinterpret_cast<const frag*>(&base[((BMB + wn * WN + b) * PL + pl) * 64 + lane]);
+#pragma unroll
+            for (int a = 0; a < WM; ++a)
+#pragma unroll
+                for (int b = 0; b < WN; ++b) T::mma(acc[a][b], fa[a], fb[b]);
+        }
+    };
+    // step t uses stage t % NS; whole trips of NS steps (stage indices fixed
+    // per trip position), then the remaining steps; every step issues its
+    // NS - 1 ahead copies (clamped past the end) so the wait count is fixed
+    constexpr int AHEAD = (NS - 2) * PER_W;     // copies issued after those of the step waited for
+    static_assert(AHEAD < 64, "in-flight copy count");
+#pragma unroll
+    for (int d = 0; d + 1 < NS; ++d) copy(d, d);
+    auto step = [&](int t, int d) {
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(AHEAD) : "memory");
+        fix(t, d);
+        // the barrier without the workgroup fence of __syncthreads(), whose
+        // release would wait for every copy in flight (vmcnt(0)): ordering
+        // here is explicit (own copies counted above, LDS accesses drained)
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        copy(t + NS - 1, (d + NS - 1) % NS);
+        contract(d);
+    };
+    const int nfull = nst - nst % NS;
+    for (int t0 = 0; t0 < nfull; t0 += NS) {
+#pragma unroll
+        for (int d = 0; d < NS; ++d) step(t0 + d, d);
+    }
+#pragma unroll
+    for (int d = 0; d + 1 < NS; ++d)
+        if (d < nst - nfull) step(nfull + d, d);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no copy outlives the workgroup's LDS
+
+    const int64_t rb0 = rbB + wm * WM, cb0 = cbB + wn * WN;
+    store_tile<PREC, WM, WN>(acc, lane, rb0, cb0, P, Q, R, ldr, beta);
 }
 
 // Kernel body selector: KIND 0 = direct fragment loads, 1 = LDS-staged with
-// loads two steps ahead, 2 = LDS-staged with loads four steps ahead.
+// loads two steps ahead, 2 = LDS-staged with loads four steps ahead, 3 = LDS
+// ring filled by direct global-to-LDS copies.
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 __device__ __forceinline__ void gemm_any(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
@@ -486,9 +619,13 @@ __device__ __forceinline__ void gemm_any(
     int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
     float beta, int64_t tm, int64_t tn)
 {
-    if constexpr (KIND >= 1 && sizeof(typename MT<PREC>::frag) == 16)
-        gemm_tile_lds<PREC, WM, WN, WAVES_M, WAVES_N, KIND == 2 ? 4 : 2>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
-                                                      nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
+    if constexpr (KIND == 3 && sizeof(typename MT<PREC>::frag) == 16)
+        gemm_tile_dma<PREC, WM, WN, WAVES_M, WAVES_N, 4>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane,
+                                                         y_pb, nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
+    else if constexpr (KIND >= 1 && sizeof(typename MT<PREC>::frag) == 16)
+        gemm_tile_lds<PREC, WM, WN, WAVES_M, WAVES_N, KIND == 2 ? 4 : 2>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb,
+                                                                         y_nkb, y_plane, y_pb, nkb, kb_lo, P, Q, R,
+                                                                         ldr, beta, tm, tn);
     else
         gemm_tile<PREC, WM, WN, WAVES_M, WAVES_N>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane, y_pb,
                                                   nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
@@ -497,7 +634,10 @@ __device__ __forceinline__ void gemm_any(
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 constexpr size_t gemm_lds_bytes()
 {
-    if constexpr (KIND >= 1 && sizeof(typename MT<PREC>::frag) == 16)
+    if constexpr (KIND == 3 && sizeof(typename MT<PREC>::frag) == 16)
+        return 4ull * gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>() * (WM * WAVES_M + WN * WAVES_N) *
+               MT<PREC>::PLANES * 1024;
+    else if constexpr (KIND >= 1 && sizeof(typename MT<PREC>::frag) == 16)
         return 2ull * gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>() * (WM * WAVES_M + WN * WAVES_N) *
                MT<PREC>::PLANES * 1024;
     return 0;
@@ -561,6 +701,13 @@ __global__ PJ_GEMM_BOUNDS void gemm_grouped_kernel(
     }
 }
 
+// Dynamic LDS above the default 64 KiB has to be allowed per kernel first.
+inline int raise_lds_limit(const void* kernel, size_t lds)
+{
+    if (lds <= 65536) return 0;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess ? 0 : -1;
+}
+
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
 int launch_gemm_t(const GemmArgs& a, hipStream_t s)
 {
@@ -572,6 +719,7 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     constexpr size_t lds = gemm_lds_bytes<KIND, PREC, WM, WN, WAVES_M, WAVES_N>();
     using OT = typename MT<PREC>::out_t;
     const int ns = a.nsplit > 1 && a.part ? a.nsplit : 1;
+    if (raise_lds_limit((const void*)gemm_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>, lds) != 0) return -1;
     hipLaunchKernelGGL((gemm_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>), dim3((unsigned)ntiles, (unsigned)ns),
                        dim3(64 * WAVES_M * WAVES_N), lds, s,
                        (const char*)a.X, a.gx.nrb, a.gx.nkb, a.gx.plane_bytes + a.gx.scale_plane, a.gx.plane_bytes,
@@ -588,7 +736,7 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
 
 }  // namespace
 
-// Tile configurations: (kind: 0 direct fragment loads, 1 / 2 LDS-staged; MFMA
+// Tile configurations: (kind: 0 direct fragment loads, 1 - 3 LDS-staged; MFMA
 // blocks per wave along M, along N; waves along M, along N; minimum resident
 // workgroups per CU).  The workgroup tile is RB*WM*WAVES_M x RB*WN*WAVES_N.
 // FP8 runs the LDS kinds as direct.
@@ -596,7 +744,7 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     X(0, 0, 2, 2, 2, 2, 2)   \
     X(1, 0, 4, 2, 2, 2, 1)   \
     X(2, 0, 2, 4, 2, 2, 1)   \
-    X(3, 0, 4, 4, 2, 2, 1)   \
+    X(3, 3, 2, 4, 2, 2, 1)   \
     X(4, 0, 2, 2, 1, 1, 2)   \
     X(5, 0, 1, 1, 2, 2, 2)   \
     X(6, 1, 2, 2, 2, 2, 2)   \
@@ -605,9 +753,9 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     X(9, 1, 2, 2, 2, 4, 1)   \
     X(10, 1, 2, 2, 4, 2, 1)  \
     X(11, 2, 2, 2, 2, 2, 2)  \
-    X(12, 2, 2, 4, 2, 2, 1)  \
-    X(13, 2, 4, 2, 2, 2, 1)  \
-    X(14, 2, 4, 4, 2, 2, 1)  \
+    X(12, 3, 2, 2, 4, 2, 1)  \
+    X(13, 3, 2, 2, 2, 2, 2)  \
+    X(14, 3, 4, 2, 2, 2, 1)  \
     X(15, 2, 2, 2, 4, 2, 1)
 
 namespace {
@@ -624,6 +772,8 @@ int launch_grouped_t(const GroupedProblem* probs, const GroupedItem* items, int6
                      hipStream_t s)
 {
     constexpr size_t lds = gemm_lds_bytes<KIND, PREC, WM, WN, WAVES_M, WAVES_N>();
+    if (raise_lds_limit((const void*)gemm_grouped_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>, lds) != 0)
+        return -1;
     hipLaunchKernelGGL((gemm_grouped_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>), dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), lds, s, probs, items, nitems);
     return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -691,7 +841,9 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
     const bool fill256 = cdiv(P, 256) * cdiv(Q, 128) >= 256;   // 256 x 128 tiles still cover the chip
     switch (prec) {
     case P_F64: return 10;                                 // LDS, 8 waves, 128 x 64 (16 x 16 blocks)
-    case P_F32: return 10;                                 // LDS 256 x 128, 8 waves
+    case P_F32:
+        if (!fill256) return 0;
+        return nkb >= 256 ? 12 : 10;                       // long: LDS ring by direct copies; else LDS 8 waves
     case P_FP8:
     case P_FP8X2: return 9;                                // 128 x 256, 8 waves, fragments direct
     case P_BF16X3:
@@ -700,7 +852,7 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
         return nkb >= 128 ? 2 : 9;                         // long: direct 128 x 256; else LDS 8 waves
     default:                                               // BF16, FP16
         if (!fill256) return 0;                            // direct 128 x 128
-        return nkb >= 128 ? 15 : 9;                        // long: loads four steps ahead
+        return nkb >= 128 ? 13 : 9;                        // long: LDS ring by direct copies, 2 per CU
     }
 }
 
