@@ -149,7 +149,7 @@ def profile_case(case, dev, iters=5):
               for i, (m, w, k) in enumerate(shapes)]
         bb = pg.Basis("dct2", 16)
         for prec, r in [("bf16x3", 4), ("bf16", 16)]:
-            cfg = autotune.tune_batched(As, Bs, r, bb, prec=prec, reps=2, candidates=[0, 5, 6, 9])
+            cfg = autotune.tune_batched(As, Bs, r, bb, prec=prec, reps=2, candidates=[0, 6, 9, 11, 13])
             outs = pg.gemm_batched(As, Bs, r, bb, prec=prec, tile_cfg=cfg)
             ws = torch.empty(pg.gemm_batched_workspace_bytes(pg._descs(As, Bs, outs), 16, r, prec, cfg),
                              dtype=torch.uint8, device=dev)
@@ -646,7 +646,7 @@ def main():
         rows = []
         plan = [(p, rr) for p in ("bf16x3", "bf16") for rr in (1, 2, 4, 8, 16)] + [("fp8", rr) for rr in (1, 2, 4, 8)]
         for prec, rr in plan:
-            cfg_b = autotune.tune_batched(As, Bs, rr, bb, prec=prec, reps=2, candidates=[0, 5, 6, 9])
+            cfg_b = autotune.tune_batched(As, Bs, rr, bb, prec=prec, reps=2, candidates=[0, 6, 9, 11, 13])
             outs = pg.gemm_batched(As, Bs, rr, bb, prec=prec, tile_cfg=cfg_b)
             descs = pg._descs(As, Bs, outs)
             ws = torch.empty(pg.gemm_batched_workspace_bytes(descs, Lb, rr, prec, cfg_b), dtype=torch.uint8,

@@ -291,6 +291,20 @@ size_t pj_gemm_batched_workspace_bytes(int count, const pj_gemm_desc* problems, 
 int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems, float beta, int prec,
                       int tile_cfg, void* ws, size_t ws_bytes, void* stream);
 
+/* The persistent launch runs each problem's output tiles either in the tile
+ * of configuration tile_cfg or in its small tile (one 32 x 32 MFMA block per
+ * wave on the same waves: 64 x 64 for four-wave configurations), so that
+ * problems whose sides the large tile would mostly pad get tiles of their own
+ * size within the same launch (paper Sec. II-A: the block size is a tuned,
+ * per-case choice).  proj_gemm_batched picks per problem by padded area;
+ * proj_gemm_batched_tiles takes the choice from `small` (host array of
+ * `count` bytes, nonzero = small tile), e.g. from the autotuner.  Workspace
+ * and errors as proj_gemm_batched; a NULL `small` is PJ_ERR_ARG (0 bytes). */
+size_t pj_gemm_batched_tiles_workspace_bytes(int count, const pj_gemm_desc* problems, const unsigned char* small,
+                                             int L, int r, int prec, int tile_cfg);
+int proj_gemm_batched_tiles(pj_basis b, int r, int count, const pj_gemm_desc* problems, const unsigned char* small,
+                            float beta, int prec, int tile_cfg, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------- projected cross-correlation */
 
 /* Bytes of workspace proj_conv1d needs (0 for invalid arguments); that of

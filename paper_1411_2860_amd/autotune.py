@@ -19,7 +19,7 @@ import os
 import threading
 
 __all__ = ["cache_path", "shape_key", "batch_key", "lookup", "record", "tune_gemm", "tune_batched",
-           "clear_memory_cache"]
+           "tune_batched_tiles", "clear_memory_cache"]
 
 _lock = threading.Lock()
 _mem: dict | None = None
@@ -159,3 +159,48 @@ def tune_batched(As, Bs, r: int, basis, prec: str = "bf16", transA=False, transB
     best = pick(times)
     record(key, best, times)
     return best
+
+
+def tune_batched_tiles(As, Bs, r: int, basis, prec: str = "bf16", tile_cfg: int = 0, transA=False, transB=False,
+                       reps: int = 3, force: bool = False):
+    """Per-problem tile of a batch for the persistent launch of `tile_cfg`:
+    times each problem alone with the configuration's tile and with its small
+    tile and keeps the faster (one flag per problem, True = small), cached
+    per batch."""
+    from . import projgemm as pg
+    shapes = []
+    for A, B in zip(As, Bs):
+        M, K = (A.shape[1], A.shape[0]) if transA else tuple(A.shape)
+        W = B.shape[0] if transB else B.shape[1]
+        shapes.append((M, W, K))
+    key = batch_key(shapes, basis.L, r, prec) + f"/tiles/c{int(tile_cfg)}"
+    if not force:
+        with _lock:
+            v = _load().get(key)
+        if v is not None and len(v.get("small", [])) == len(shapes):
+            return [bool(f) for f in v["small"]]
+    flags, ms = [], []
+    for A, B in zip(As, Bs):
+        outs = pg.gemm_batched([A], [B], r, basis, prec=prec, transA=transA, transB=transB, tile_cfg=tile_cfg,
+                               small=[False])
+        t = []
+        for f in (False, True):
+            need = pg.gemm_batched_workspace_bytes(pg._descs([A], [B], outs, transA, transB), basis.L, r, prec,
+                                                   tile_cfg, [f])
+            ws = pg._byte_buffer(need, A.device)
+            t.append(_time_ms(lambda: pg.gemm_batched([A], [B], r, basis, prec=prec, transA=transA, transB=transB,
+                                                      outs=outs, tile_cfg=tile_cfg, workspace=ws, small=[f]),
+                              reps, warmup=1))
+            del ws
+        flags.append(t[1] < t[0] * 0.97)
+        ms.append([round(t[0], 5), round(t[1], 5)])
+    with _lock:
+        d = _load()
+        d[key] = {"small": [int(f) for f in flags], "ms": ms}
+        path = cache_path()
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return flags

@@ -624,9 +624,20 @@ namespace {
 struct BatchPlan {
     size_t pack_table, probs_off, items_off, ops_off, total;
     std::vector<size_t> a_off, b_off;
+    std::vector<unsigned char> small;   // per problem: the small tile body
     int64_t nitems;
     int cfg;
 };
+
+// Automatic per-problem body: the small tile when the configuration's tile
+// pads the problem's M x W to more than 1.6 times the area the small tile
+// pads it to (about the small body's loss of rate per unit of area).
+bool prefer_small(int M, int W, int tm, int tn, int sm, int sn)
+{
+    const double big = (double)rup(M, tm) * (double)rup(W, tn);
+    const double small = (double)rup(M, sm) * (double)rup(W, sn);
+    return big > 1.6 * small;
+}
 
 int check_desc(const pj_gemm_desc& d)
 {
@@ -639,7 +650,8 @@ int check_desc(const pj_gemm_desc& d)
     return PJ_OK;
 }
 
-int plan_batch(int count, const pj_gemm_desc* p, int L, int r, int prec, int tile_cfg, BatchPlan& bp)
+int plan_batch(int count, const pj_gemm_desc* p, int L, int r, int prec, int tile_cfg, BatchPlan& bp,
+               const unsigned char* small = nullptr)
 {
     if (count < 1 || !p) return PJ_ERR_ARG;
     if (L < 1 || L > kMaxL || r < 1 || r > L || !valid_prec(prec)) return PJ_ERR_ARG;
@@ -651,17 +663,22 @@ int plan_batch(int count, const pj_gemm_desc* p, int L, int r, int prec, int til
     if ((prec == PJ_FP8 || prec == PJ_FP8X2) && r > 8) return PJ_ERR_UNSUPPORTED;
     bp.cfg = tile_cfg;
     if (bp.cfg < 0) bp.cfg = 0;
-    int tm = 0, tn = 0;
+    int tm = 0, tn = 0, sm = 0, sn = 0;
     gemm_config_tile(prec, bp.cfg, &tm, &tn);
+    gemm_config_small_tile(prec, bp.cfg, &sm, &sn);
     bp.nitems = 0;
     bp.a_off.resize(count);
     bp.b_off.resize(count);
+    bp.small.resize(count);
+    for (int i = 0; i < count; ++i)
+        bp.small[i] = small ? (small[i] ? 1 : 0) : (prefer_small(p[i].M, p[i].W, tm, tn, sm, sn) ? 1 : 0);
     size_t off = 0;
     bp.pack_table = rup((int64_t)pack_grouped_table_bytes(2 * count), 256);
     off += bp.pack_table;
     bp.probs_off = off;
     off += rup((int64_t)sizeof(GroupedProblem) * count, 256);
-    for (int i = 0; i < count; ++i) bp.nitems += cdiv(p[i].M, tm) * cdiv(p[i].W, tn);
+    for (int i = 0; i < count; ++i)
+        bp.nitems += bp.small[i] ? cdiv(p[i].M, sm) * cdiv(p[i].W, sn) : cdiv(p[i].M, tm) * cdiv(p[i].W, tn);
     bp.items_off = off;
     off += rup((int64_t)sizeof(GroupedItem) * bp.nitems, 256);
     bp.ops_off = off;
@@ -697,12 +714,36 @@ size_t pj_gemm_batched_workspace_bytes(int count, const pj_gemm_desc* problems, 
     return bp.total;
 }
 
+size_t pj_gemm_batched_tiles_workspace_bytes(int count, const pj_gemm_desc* problems, const unsigned char* small,
+                                             int L, int r, int prec, int tile_cfg)
+{
+    BatchPlan bp;
+    if (!small || plan_batch(count, problems, L, r, prec, tile_cfg, bp, small) != PJ_OK) return 0;
+    return bp.total;
+}
+
+static int run_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems, float beta, int prec,
+                       int tile_cfg, const unsigned char* small, void* ws, size_t ws_bytes, void* stream);
+
 int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems, float beta, int prec,
                       int tile_cfg, void* ws, size_t ws_bytes, void* stream)
 {
+    return run_batched(b, r, count, problems, beta, prec, tile_cfg, nullptr, ws, ws_bytes, stream);
+}
+
+int proj_gemm_batched_tiles(pj_basis b, int r, int count, const pj_gemm_desc* problems, const unsigned char* small,
+                            float beta, int prec, int tile_cfg, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!small) return PJ_ERR_ARG;
+    return run_batched(b, r, count, problems, beta, prec, tile_cfg, small, ws, ws_bytes, stream);
+}
+
+static int run_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems, float beta, int prec,
+                       int tile_cfg, const unsigned char* small, void* ws, size_t ws_bytes, void* stream)
+{
     if (!b) return PJ_ERR_ARG;
     BatchPlan bp;
-    int rc = plan_batch(count, problems, b->L, r, prec, tile_cfg, bp);
+    int rc = plan_batch(count, problems, b->L, r, prec, tile_cfg, bp, small);
     if (rc != PJ_OK) return rc;
     if (!ws || ws_bytes < bp.total) return PJ_ERR_WORKSPACE;
     if (!b->on_device) return PJ_ERR_HIP;
@@ -711,8 +752,9 @@ int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems
     const Layout ly = layout_of(prec);
     std::vector<PackArgs> pa(2 * (size_t)count);
     std::vector<GroupedProblem> gp(count);
-    int tm = 0, tn = 0;
+    int tm = 0, tn = 0, sm = 0, sn = 0;
     gemm_config_tile(prec, bp.cfg, &tm, &tn);
+    gemm_config_small_tile(prec, bp.cfg, &sm, &sn);
     std::vector<GroupedItem> items;
     items.reserve(bp.nitems);
     for (int i = 0; i < count; ++i) {
@@ -728,9 +770,10 @@ int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems
         g.y_plane = gb.plane_bytes + gb.scale_plane; g.y_pb = gb.plane_bytes;
         g.nkb = (int64_t)r * ga.Gp / ly.KB;
         g.P = d.M; g.Q = d.W; g.R = d.R; g.ldr = d.ldr; g.beta = beta;
-        const int64_t ntm = cdiv(d.M, tm), ntn = cdiv(d.W, tn);
+        const int body = bp.small[i];
+        const int64_t ntm = cdiv(d.M, body ? sm : tm), ntn = cdiv(d.W, body ? sn : tn);
         for (int64_t y = 0; y < ntn; ++y)
-            for (int64_t x = 0; x < ntm; ++x) items.push_back(GroupedItem{i, (int32_t)x, (int32_t)y});
+            for (int64_t x = 0; x < ntm; ++x) items.push_back(GroupedItem{i, (int32_t)x, (int32_t)y, body});
     }
     // longest contractions first (stable: problem order, then tile order)
     std::stable_sort(items.begin(), items.end(), [&](const GroupedItem& u, const GroupedItem& v) {
@@ -745,9 +788,8 @@ int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems
         hipMemcpyAsync(w + bp.items_off, items.data(), sizeof(GroupedItem) * items.size(), hipMemcpyHostToDevice,
                        st) != hipSuccess)
         return PJ_ERR_HIP;
-    const int64_t grid = std::min<int64_t>(bp.nitems, 2 * (int64_t)device_cus());
     rc = launch_gemm_grouped(prec, (const GroupedProblem*)(w + bp.probs_off), (const GroupedItem*)(w + bp.items_off),
-                             bp.nitems, grid, bp.cfg, st);
+                             bp.nitems, device_cus(), bp.cfg, st);
     return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
 }
 

@@ -170,15 +170,20 @@ struct GroupedProblem {
 };
 struct GroupedItem {
     int32_t prob;
-    int32_t tm, tn;
-};
+    int32_t tm, tn;      // tile of the item's body
+    int32_t body;        // 0: the launch's tile configuration; 1: its small tile
+};                       // (one MFMA block per wave, same waves)
+// Persistent launch over `nitems` items: as many workgroups as `cus` compute
+// units hold at once (at most one per item).
 int launch_gemm_grouped(int prec, const GroupedProblem* probs, const GroupedItem* items, int64_t nitems,
-                        int64_t grid, int cfg, hipStream_t s);
+                        int64_t cus, int cfg, hipStream_t s);
 
 // cfg < 0 picks the default tile configuration for the shape.
 int launch_gemm(int prec, const GemmArgs& a, int cfg, hipStream_t s);
 int gemm_num_configs();
 int gemm_config_tile(int prec, int cfg, int* tile_m, int* tile_n);
+// The small tile grouped launches of configuration cfg can also run.
+int gemm_config_small_tile(int prec, int cfg, int* tile_m, int* tile_n);
 int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb);
 int gemm_split_count(int prec, int64_t P, int64_t Q, int64_t nkb, int cfg);
 

@@ -687,7 +687,10 @@ __global__ __launch_bounds__(256) void gemm_split_sum_kernel(const OT* __restric
 
 // Persistent grouped launch: workgroup b processes items b, b + grid, ... of
 // a list of (problem, tile) items sorted by decreasing contraction length, so
-// the longest tiles start first and the tail is made of short ones.
+// the longest tiles start first and the tail is made of short ones.  Each
+// item names its body: the configuration's tile, or the small tile of one
+// MFMA block per wave on the same waves (for problems whose sides the large
+// tile would mostly pad).
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
 __global__ PJ_GEMM_BOUNDS void gemm_grouped_kernel(
     const GroupedProblem* __restrict__ probs, const GroupedItem* __restrict__ items, int64_t nitems)
@@ -695,9 +698,14 @@ __global__ PJ_GEMM_BOUNDS void gemm_grouped_kernel(
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const GroupedItem w = items[it];
         const GroupedProblem& p = probs[w.prob];
-        gemm_any<KIND, PREC, WM, WN, WAVES_M, WAVES_N>(
-            (const char*)p.X, p.x_nrb, p.x_nkb, p.x_plane, p.x_pb, (const char*)p.Y, p.y_nrb, p.y_nkb, p.y_plane,
-            p.y_pb, p.nkb, 0, p.P, p.Q, (typename MT<PREC>::out_t*)p.R, p.ldr, p.beta, w.tm, w.tn);
+        if (w.body == 0)
+            gemm_any<KIND, PREC, WM, WN, WAVES_M, WAVES_N>(
+                (const char*)p.X, p.x_nrb, p.x_nkb, p.x_plane, p.x_pb, (const char*)p.Y, p.y_nrb, p.y_nkb,
+                p.y_plane, p.y_pb, p.nkb, 0, p.P, p.Q, (typename MT<PREC>::out_t*)p.R, p.ldr, p.beta, w.tm, w.tn);
+        else
+            gemm_any<0, PREC, 1, 1, WAVES_M, WAVES_N>(
+                (const char*)p.X, p.x_nrb, p.x_nkb, p.x_plane, p.x_pb, (const char*)p.Y, p.y_nrb, p.y_nkb,
+                p.y_plane, p.y_pb, p.nkb, 0, p.P, p.Q, (typename MT<PREC>::out_t*)p.R, p.ldr, p.beta, w.tm, w.tn);
     }
 }
 
@@ -768,24 +776,30 @@ constexpr TileCfg kTileCfgs[] = {
 constexpr int kNumTileCfgs = (int)(sizeof(kTileCfgs) / sizeof(kTileCfgs[0]));
 
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
-int launch_grouped_t(const GroupedProblem* probs, const GroupedItem* items, int64_t nitems, int64_t grid,
+int launch_grouped_t(const GroupedProblem* probs, const GroupedItem* items, int64_t nitems, int64_t cus,
                      hipStream_t s)
 {
     constexpr size_t lds = gemm_lds_bytes<KIND, PREC, WM, WN, WAVES_M, WAVES_N>();
-    if (raise_lds_limit((const void*)gemm_grouped_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>, lds) != 0)
-        return -1;
+    const void* kern = (const void*)gemm_grouped_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>;
+    if (raise_lds_limit(kern, lds) != 0) return -1;
+    // as many persistent workgroups as the CUs hold at once (registers, LDS)
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WAVES_M * WAVES_N, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t grid = std::min<int64_t>(nitems, (int64_t)per_cu * cus);
     hipLaunchKernelGGL((gemm_grouped_kernel<KIND, PREC, WM, WN, WAVES_M, WAVES_N, OCC>), dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), lds, s, probs, items, nitems);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int PREC>
-int launch_grouped_cfg(const GroupedProblem* probs, const GroupedItem* items, int64_t nitems, int64_t grid, int cfg,
+int launch_grouped_cfg(const GroupedProblem* probs, const GroupedItem* items, int64_t nitems, int64_t cus, int cfg,
                        hipStream_t s)
 {
     switch (cfg) {
 #define PJ_CFG_CASE(i, k_, a_, b_, c_, d_, o_) \
-    case i: return launch_grouped_t<k_, PREC, a_, b_, c_, d_, o_>(probs, items, nitems, grid, s);
+    case i: return launch_grouped_t<k_, PREC, a_, b_, c_, d_, o_>(probs, items, nitems, cus, s);
         PJ_GEMM_CONFIGS(PJ_CFG_CASE)
 #undef PJ_CFG_CASE
     default: return -2;
@@ -808,17 +822,17 @@ int launch_cfg(const GemmArgs& a, int cfg, hipStream_t s)
 int gemm_num_configs() { return kNumTileCfgs; }
 
 int launch_gemm_grouped(int prec, const GroupedProblem* probs, const GroupedItem* items, int64_t nitems,
-                        int64_t grid, int cfg, hipStream_t s)
+                        int64_t cus, int cfg, hipStream_t s)
 {
     switch (prec) {
-    case P_F64:    return launch_grouped_cfg<P_F64>(probs, items, nitems, grid, cfg, s);
-    case P_F32:    return launch_grouped_cfg<P_F32>(probs, items, nitems, grid, cfg, s);
-    case P_BF16:   return launch_grouped_cfg<P_BF16>(probs, items, nitems, grid, cfg, s);
-    case P_BF16X3: return launch_grouped_cfg<P_BF16X3>(probs, items, nitems, grid, cfg, s);
-    case P_F16:    return launch_grouped_cfg<P_F16>(probs, items, nitems, grid, cfg, s);
-    case P_F16X3:  return launch_grouped_cfg<P_F16X3>(probs, items, nitems, grid, cfg, s);
-    case P_FP8:    return launch_grouped_cfg<P_FP8>(probs, items, nitems, grid, cfg, s);
-    case P_FP8X2:  return launch_grouped_cfg<P_FP8X2>(probs, items, nitems, grid, cfg, s);
+    case P_F64:    return launch_grouped_cfg<P_F64>(probs, items, nitems, cus, cfg, s);
+    case P_F32:    return launch_grouped_cfg<P_F32>(probs, items, nitems, cus, cfg, s);
+    case P_BF16:   return launch_grouped_cfg<P_BF16>(probs, items, nitems, cus, cfg, s);
+    case P_BF16X3: return launch_grouped_cfg<P_BF16X3>(probs, items, nitems, cus, cfg, s);
+    case P_F16:    return launch_grouped_cfg<P_F16>(probs, items, nitems, cus, cfg, s);
+    case P_F16X3:  return launch_grouped_cfg<P_F16X3>(probs, items, nitems, cus, cfg, s);
+    case P_FP8:    return launch_grouped_cfg<P_FP8>(probs, items, nitems, cus, cfg, s);
+    case P_FP8X2:  return launch_grouped_cfg<P_FP8X2>(probs, items, nitems, cus, cfg, s);
     default:       return -2;
     }
 }
@@ -829,6 +843,15 @@ int gemm_config_tile(int prec, int cfg, int* tile_m, int* tile_n)
     const int rb = layout_of(prec).RB;
     *tile_m = rb * kTileCfgs[cfg].wm * kTileCfgs[cfg].wavm;
     *tile_n = rb * kTileCfgs[cfg].wn * kTileCfgs[cfg].wavn;
+    return 0;
+}
+
+int gemm_config_small_tile(int prec, int cfg, int* tile_m, int* tile_n)
+{
+    if (cfg < 0 || cfg >= kNumTileCfgs) return -1;
+    const int rb = layout_of(prec).RB;
+    *tile_m = rb * kTileCfgs[cfg].wavm;
+    *tile_n = rb * kTileCfgs[cfg].wavn;
     return 0;
 }
 

@@ -904,6 +904,169 @@ int launch_p(const PackArgs* a, int n, hipStream_t s)
 }
 
 
+// ---- transposed sources, column-wise -----------------------------------------
+// A source stored with the contraction index along its rows (X[k * ld + p]:
+// the B side of a GEMM whose B is K x W) is projected one column p per
+// thread: each group of L consecutive source rows is read as L coalesced row
+// segments (256 columns, any alignment) and combined into RL projections at
+// a time with vector FMAs, the coefficients broadcast from LDS; a thread
+// keeps the E consecutive groups of one lane vector and writes it, so the 32
+// threads of a row block write one contiguous half-tile.  Workgroup = 256
+// columns x one k-block of groups, for every projection.
+constexpr int kColW = 256;
+constexpr int kColRL = 16;
+constexpr int kColMaxL = 256;   // the library's largest projection size
+
+template <typename TIn>
+struct ColJob {
+    const TIn* X; int64_t ld;
+    int64_t P, K;
+    int L, r;
+    const TIn* coef;        // L x L, element (t, l)
+    char* out;
+    int64_t nkb, Gp, plane_stride;
+    int64_t ncol;           // column tiles
+    TIn* keep; int64_t keep_ld;
+};
+
+template <typename TIn, int PREC>
+__device__ __forceinline__ void colpack_tile(const ColJob<TIn>& J, int64_t tix)
+{
+    constexpr Layout ly = layout_of(PREC);
+    constexpr int KB = ly.KB, RB = ly.RB, E = ly.E;
+    static_assert(KB % E == 0 && E <= 8, "lane vectors of at most 8 values");
+    __shared__ TIn cs[kColMaxL * kColRL];   // coefficients of the pass: [t][l - l0]
+    const int64_t ct = tix % J.ncol, gt = tix / J.ncol;
+    const int64_t p = ct * kColW + threadIdx.x;
+    const int64_t j0 = gt * KB;
+    const int L = J.L, r = J.r;
+    const bool live = p < J.P;
+    const int64_t pc = live ? p : J.P - 1;   // reads stay inside the source
+    for (int l0 = 0; l0 < r; l0 += kColRL) {
+        __syncthreads();
+        for (int x = threadIdx.x; x < L * kColRL; x += kColW) {
+            const int t = x / kColRL, lq = x % kColRL;
+            cs[x] = l0 + lq < r ? J.coef[(int64_t)t * L + l0 + lq] : (TIn)0;
+        }
+        __syncthreads();
+        for (int g0 = 0; g0 < KB; g0 += E) {
+            TIn acc[kColRL][E];
+#pragma unroll
+            for (int q = 0; q < kColRL; ++q)
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[q][e] = (TIn)0;
+            // rows past K read row K - 1 and count as zero; the loads of
+            // index t + 1 are issued before the products of index t
+            auto ld = [&](int t, TIn (&x)[E]) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int64_t k = (j0 + g0 + e) * L + t;
+                    x[e] = J.X[(k < J.K ? k : J.K - 1) * J.ld + pc];
+                }
+            };
+            auto fma = [&](int t, const TIn (&x)[E]) {
+                const TIn* c = cs + t * kColRL;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const TIn xe = (j0 + g0 + e) * L + t < J.K ? x[e] : (TIn)0;
+#pragma unroll
+                    for (int q = 0; q < kColRL; ++q) acc[q][e] += c[q] * xe;
+                }
+            };
+            TIn xa[E], xb[E];
+            ld(0, xa);
+            for (int t = 0; t < L; t += 2) {
+                if (t + 1 < L) ld(t + 1, xb);
+                fma(t, xa);
+                if (t + 1 < L) {
+                    if (t + 2 < L) ld(t + 2, xa);
+                    fma(t + 1, xb);
+                }
+            }
+            if (live) {
+                const int64_t rb = p / RB;
+                const int rib = (int)(p % RB), g = g0 / E;
+#pragma unroll
+                for (int q = 0; q < kColRL; ++q) {
+                    const int l = l0 + q;
+                    if (l >= r) break;
+                    const int64_t kb = ((int64_t)l * J.Gp + j0) / KB;
+                    const int64_t off = ((rb * J.nkb + kb) * 64 + g * RB + rib) * (int64_t)ly.LB;
+                    store_lane<PREC, E, TIn>(J.out, off, J.plane_stride, 0, acc[q]);
+                    if (J.keep) {
+                        TIn* dst = J.keep + p * J.keep_ld + (int64_t)l * J.Gp + j0 + g0;
+#pragma unroll
+                        for (int e = 0; e < E; ++e) dst[e] = acc[q][e];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename TIn, int PREC>
+__global__ __launch_bounds__(kColW) void colpack_grouped_kernel(const ColJob<TIn>* __restrict__ jobs,
+                                                               const int64_t* __restrict__ prefix, int njobs)
+{
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    colpack_tile<TIn, PREC>(jobs[lo], b - prefix[lo]);
+}
+
+template <typename TIn, int PREC>
+ColJob<TIn> make_coljob(const PackArgs& a)
+{
+    ColJob<TIn> j;
+    j.X = (const TIn*)a.X;
+    j.ld = a.ld;
+    j.P = a.P;
+    j.K = a.K;
+    j.L = a.L;
+    j.r = a.r;
+    j.coef = (const TIn*)a.coef;
+    j.out = (char*)a.out;
+    j.nkb = a.geom.nkb;
+    j.Gp = a.geom.Gp;
+    j.plane_stride = a.geom.plane_bytes + a.geom.scale_plane;
+    j.ncol = cdiv(a.P, kColW);
+    j.keep = (TIn*)a.keep;
+    j.keep_ld = a.keep_ld;
+    return j;
+}
+
+// Formats the column-wise path serves (16-byte lane vectors of at most 8 values).
+template <int PREC>
+constexpr bool colpack_ok() { return layout_of(PREC).E <= 8; }
+
+template <typename TIn, int PREC>
+int launch_colpack_grouped(const PackArgs* a, int n, char* jobs_at, char* prefix_at, hipStream_t s)
+{
+    if constexpr (!colpack_ok<PREC>()) {
+        return -2;
+    } else {
+        std::vector<ColJob<TIn>> jobs(n);
+        std::vector<int64_t> prefix(n + 1, 0);
+        for (int i = 0; i < n; ++i) {
+            jobs[i] = make_coljob<TIn, PREC>(a[i]);
+            prefix[i + 1] = prefix[i] + jobs[i].ncol * (a[i].geom.Gp / layout_of(PREC).KB);
+        }
+        if (prefix[n] == 0) return 0;
+        if (prefix[n] > 0x7fffffff) return -2;
+        if (hipMemcpyAsync(jobs_at, jobs.data(), sizeof(ColJob<TIn>) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(prefix_at, prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s) !=
+                hipSuccess)
+            return -1;
+        hipLaunchKernelGGL((colpack_grouped_kernel<TIn, PREC>), dim3((unsigned)prefix[n]), dim3(kColW), 0, s,
+                           (const ColJob<TIn>*)jobs_at, (const int64_t*)prefix_at, n);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
+}
+
 template <typename TIn, int PREC, int RL, int NCH>
 int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
 {
@@ -957,8 +1120,38 @@ int launch_grouped_t(const PackArgs* a, int n, void* table, hipStream_t s)
     return 0;
 }
 
+size_t pack_grouped_table_bytes_rows(int n)
+{
+    return (size_t)rup((int64_t)sizeof(PackJob<double>) * n, 256) + 3 * (size_t)rup(8 * (int64_t)(n + 1), 256);
+}
+
+template <typename TIn, int PREC>
+int launch_grouped_rows(const PackArgs* a, int n, void* table, hipStream_t s);
+
 template <typename TIn, int PREC>
 int launch_grouped_p(const PackArgs* a, int n, void* table, hipStream_t s)
+{
+    if constexpr (colpack_ok<PREC>()) {
+        // transposed sources go column-wise; the rest through the tile packer
+        std::vector<PackArgs> rows, cols;
+        for (int i = 0; i < n; ++i) (a[i].trans ? cols : rows).push_back(a[i]);
+        if (!cols.empty()) {
+            char* t = (char*)table;
+            const size_t base = pack_grouped_table_bytes_rows(n);
+            const int e = launch_colpack_grouped<TIn, PREC>(cols.data(), (int)cols.size(), t + base,
+                                                            t + base + rup((int64_t)sizeof(ColJob<double>) * n, 256), s);
+            if (e != 0) return e;
+            if (rows.empty()) return 0;
+            a = rows.data();
+            n = (int)rows.size();
+            return launch_grouped_rows<TIn, PREC>(a, n, table, s);
+        }
+    }
+    return launch_grouped_rows<TIn, PREC>(a, n, table, s);
+}
+
+template <typename TIn, int PREC>
+int launch_grouped_rows(const PackArgs* a, int n, void* table, hipStream_t s)
 {
     int r = 1;
     for (int i = 0; i < n; ++i) r = a[i].r > r ? a[i].r : r;
@@ -1101,8 +1294,10 @@ int launch_pack(int prec, const PackArgs& a, hipStream_t s) { return launch_pack
 
 size_t pack_grouped_table_bytes(int n)
 {
-    // the jobs, then one prefix array per round layout
-    return (size_t)rup((int64_t)sizeof(PackJob<double>) * n, 256) + 3 * (size_t)rup(8 * (int64_t)(n + 1), 256);
+    // the tile packer's jobs and one prefix array per round layout, then the
+    // column-wise jobs and their prefix array
+    return pack_grouped_table_bytes_rows(n) + (size_t)rup((int64_t)sizeof(ColJob<double>) * n, 256) +
+           (size_t)rup(8 * (int64_t)(n + 1), 256);
 }
 
 int launch_pack_grouped(int prec, const PackArgs* a, int n, void* table, hipStream_t s)

@@ -70,6 +70,8 @@ _SIGNATURES = {
     "pj_conv1d_workspace_bytes": (_sz, [_i64, _i, _i, _i, _i]),
     "pj_gemm_batched_workspace_bytes": (_sz, [_i, _vp, _i, _i, _i, _i]),
     "proj_gemm_batched": (_i, [_vp, _i, _i, _vp, _f, _i, _i, _vp, _sz, _vp]),
+    "pj_gemm_batched_tiles_workspace_bytes": (_sz, [_i, _vp, _vp, _i, _i, _i, _i]),
+    "proj_gemm_batched_tiles": (_i, [_vp, _i, _i, _vp, _vp, _f, _i, _i, _vp, _sz, _vp]),
     "pj_gemm_backward_workspace_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
     "proj_gemm_backward": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                                 _i64, _i, _vp, _sz, _vp]),
@@ -483,16 +485,29 @@ def _descs(As, Bs, Rs, transA=False, transB=False):
     return arr
 
 
-def gemm_batched_workspace_bytes(descs, L: int, r: int, prec="f32", tile_cfg=-1) -> int:
-    return int(lib().pj_gemm_batched_workspace_bytes(len(descs), ctypes.cast(descs, _vp), L, r, _prec(prec),
-                                                     int(tile_cfg)))
+def _small_arr(small, n):
+    if small is None:
+        return None
+    if len(small) != n:
+        raise ValueError(f"small needs one flag per problem ({n})")
+    return (ctypes.c_ubyte * n)(*[1 if f else 0 for f in small])
+
+
+def gemm_batched_workspace_bytes(descs, L: int, r: int, prec="f32", tile_cfg=-1, small=None) -> int:
+    sm = _small_arr(small, len(descs))
+    if sm is None:
+        return int(lib().pj_gemm_batched_workspace_bytes(len(descs), ctypes.cast(descs, _vp), L, r, _prec(prec),
+                                                         int(tile_cfg)))
+    return int(lib().pj_gemm_batched_tiles_workspace_bytes(len(descs), ctypes.cast(descs, _vp), ctypes.cast(sm, _vp),
+                                                           L, r, _prec(prec), int(tile_cfg)))
 
 
 def gemm_batched(As, Bs, r: int, basis: Basis, prec="bf16", transA=False, transB=False, outs=None, beta=0.0,
-                 tile_cfg=-1, workspace=None, stream=None):
+                 tile_cfg=-1, workspace=None, stream=None, small=None):
     """R_i = A_i Q_{r,K_i} B_i for every problem i, in grouped pack launches
-    (one per operand staging mode) and one persistent GEMM launch.  Returns
-    the list of outputs."""
+    (one per operand staging mode) and one persistent GEMM launch.  `small`
+    (one flag per problem) picks each problem's tile: the configuration's, or
+    its small one; None lets the library choose.  Returns the outputs."""
     import torch
     if outs is None:
         outs = []
@@ -501,14 +516,21 @@ def gemm_batched(As, Bs, r: int, basis: Basis, prec="bf16", transA=False, transB
             W = B.shape[0] if transB else B.shape[1]
             outs.append(torch.empty((M, W), dtype=torch.float32, device=A.device))
     descs = _descs(As, Bs, outs, transA, transB)
-    need = gemm_batched_workspace_bytes(descs, basis.L, r, prec, tile_cfg)
+    need = gemm_batched_workspace_bytes(descs, basis.L, r, prec, tile_cfg, small)
     if need == 0:
         raise ProjGemmError(-1, "pj_gemm_batched_workspace_bytes")
     if workspace is None:
         workspace = _byte_buffer(need, As[0].device)
-    _check(lib().proj_gemm_batched(basis.handle, r, len(As), ctypes.cast(descs, _vp), float(beta), _prec(prec),
-                                   int(tile_cfg), _ptr(workspace), workspace.numel(), _stream(stream)),
-           "proj_gemm_batched")
+    sm = _small_arr(small, len(As))
+    if sm is None:
+        _check(lib().proj_gemm_batched(basis.handle, r, len(As), ctypes.cast(descs, _vp), float(beta), _prec(prec),
+                                       int(tile_cfg), _ptr(workspace), workspace.numel(), _stream(stream)),
+               "proj_gemm_batched")
+    else:
+        _check(lib().proj_gemm_batched_tiles(basis.handle, r, len(As), ctypes.cast(descs, _vp), ctypes.cast(sm, _vp),
+                                             float(beta), _prec(prec), int(tile_cfg), _ptr(workspace),
+                                             workspace.numel(), _stream(stream)),
+               "proj_gemm_batched_tiles")
     return outs
 
 

@@ -197,6 +197,25 @@ def test_saved_forward_backward_validation(lib, basis16):
         assert save() == HIP and bwd() == HIP
 
 
+def test_batched_tiles_workspace(lib):
+    """Per-problem tiles: more items (and workspace) with the small tile, the
+    library's own choice between the two, NULL flags rejected."""
+    import ctypes as ct
+    descs = (pg.GemmDesc * 2)(pg.GemmDesc(300, 150, 64, b"N", b"N", FAKE, 64, FAKE, 150, FAKE, 150),
+                              pg.GemmDesc(1024, 1024, 64, b"N", b"N", FAKE, 64, FAKE, 1024, FAKE, 1024))
+    big = (ct.c_ubyte * 2)(0, 0)
+    small = (ct.c_ubyte * 2)(1, 1)
+    wb = lib.pj_gemm_batched_tiles_workspace_bytes(2, ct.cast(descs, ct.c_void_p), ct.cast(big, ct.c_void_p), 16, 4,
+                                                   1, 0)
+    ws = lib.pj_gemm_batched_tiles_workspace_bytes(2, ct.cast(descs, ct.c_void_p), ct.cast(small, ct.c_void_p), 16,
+                                                   4, 1, 0)
+    wa = lib.pj_gemm_batched_workspace_bytes(2, ct.cast(descs, ct.c_void_p), 16, 4, 1, 0)
+    assert 0 < wb < ws and wb <= wa <= ws
+    assert lib.pj_gemm_batched_tiles_workspace_bytes(2, ct.cast(descs, ct.c_void_p), None, 16, 4, 1, 0) == 0
+    assert lib.proj_gemm_batched_tiles(None, 4, 2, ct.cast(descs, ct.c_void_p), ct.cast(big, ct.c_void_p), 0.0, 1, 0,
+                                       FAKE, ws, None) == ARG
+
+
 def test_noalloc_validation_and_scratch_limit(lib, basis16):
     """proj_gemm_noalloc rejects what proj_gemm rejects, and a request whose
     workspace exceeds the fixed scratch, before any device work."""

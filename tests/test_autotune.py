@@ -55,3 +55,6 @@ def test_tune_gemm_and_batched_on_device(tmp_cache):
     Bs = [torch.from_numpy(rng.standard_normal((k, w))).float().cuda() for k, w in [(64, 50), (200, 400)]]
     c2 = autotune.tune_batched(As, Bs, 4, basis, prec="bf16", reps=1, candidates=[0, 4, 6])
     assert c2 in (0, 4, 6)
+    flags = autotune.tune_batched_tiles(As, Bs, 4, basis, prec="bf16", tile_cfg=6, reps=1)
+    assert len(flags) == 2 and all(isinstance(f, bool) for f in flags)
+    assert autotune.tune_batched_tiles(As, Bs, 4, basis, prec="bf16", tile_cfg=6) == flags     # cached

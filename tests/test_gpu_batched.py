@@ -80,17 +80,51 @@ def test_every_tile_config_and_layouts(pg, cfg):
                                f"cfg {cfg} {prec} problem {i}")
 
 
-def test_batched_equals_single_calls(pg):
-    """Same packs and the same per-tile summation order as proj_gemm."""
-    As, Bs = _small_batch(seed=5)
-    basis = pg.Basis("dct2", 16)
+@pytest.mark.parametrize("cfg", [0, 6, 9, 13])
+def test_mixed_per_problem_tiles(pg, cfg):
+    """One persistent launch running some problems in the configuration's
+    tile and the others in its small tile (alternating, and the library's own
+    choice), both layouts of B."""
+    As, Bs = _small_batch(seed=6)
+    L, r = 16, 5
+    basis = pg.Basis("dct2", L)
+    C, D = _ref.oracle_basis("dct2", L)
     Ad = [torch.from_numpy(a).float().cuda() for a in As]
-    Bd = [torch.from_numpy(b).float().cuda() for b in Bs]
-    outs = pg.gemm_batched(Ad, Bd, 5, basis, prec="bf16x3", tile_cfg=0)
-    for A, B, R in zip(Ad, Bd, outs):
-        R1 = pg.gemm(A, B, 5, basis, prec="bf16x3")
-        torch.cuda.synchronize()
-        assert torch.equal(R, R1) or float((R - R1).abs().max()) <= 1e-6 * float(R1.abs().max() + 1)
+    for transB in (False, True):
+        Bd = [torch.from_numpy(np.ascontiguousarray(b.T if transB else b)).float().cuda() for b in Bs]
+        for small in ([i % 2 == 0 for i in range(len(As))], [True] * len(As), None):
+            for prec in ("f32", "bf16"):
+                outs = pg.gemm_batched(Ad, Bd, r, basis, prec=prec, transB=transB, tile_cfg=cfg, small=small)
+                torch.cuda.synchronize()
+                for i, (A, B, R) in enumerate(zip(As, Bs, outs)):
+                    ref = oracle.gemm_proj(A, B, C, D, r)
+                    _tol.assert_within(R.double().cpu().numpy(), ref, _bound(prec, A, B, C, D, r, L),
+                                       f"cfg {cfg} {prec} small={small} transB={transB} problem {i}")
+
+
+def test_batched_equals_single_calls(pg):
+    """The batch computes what proj_gemm computes: the same basis, the same
+    contraction order; B sides stored K x W are projected column-wise in the
+    batch, so the packed values may differ from the single call's in their
+    FP32 rounding, and the two results agree within twice the rounding bound
+    of one (identical where the packs are).  A stored transposed goes
+    column-wise too; with B stored W x K both paths pack identically."""
+    As, Bs = _small_batch(seed=5)
+    L, r = 16, 5
+    basis = pg.Basis("dct2", L)
+    C, D = _ref.oracle_basis("dct2", L)
+    Ad = [torch.from_numpy(a).float().cuda() for a in As]
+    for transB in (False, True):
+        Bd = [torch.from_numpy(np.ascontiguousarray(b.T if transB else b)).float().cuda() for b in Bs]
+        outs = pg.gemm_batched(Ad, Bd, r, basis, prec="bf16x3", transB=transB, tile_cfg=0, small=[False] * len(As))
+        for i, (A, B, Ag, Bg, R) in enumerate(zip(As, Bs, Ad, Bd, outs)):
+            R1 = pg.gemm(Ag, Bg, r, basis, prec="bf16x3", transB=transB)
+            torch.cuda.synchronize()
+            if transB:
+                assert torch.equal(R, R1), f"problem {i}: same packs, same tile, different result"
+            else:
+                _tol.assert_within(R.double().cpu().numpy(), R1.double().cpu().numpy(),
+                                   2.0 * _bound("bf16x3", A, B, C, D, r, L), f"problem {i} batch vs single")
 
 
 @pytest.fixture(scope="module")
