@@ -440,6 +440,35 @@ int pj_block_moments(int L, int64_t rows, int64_t K, const float* X, int64_t ld,
  * non-symmetric M).  Uploads synchronously, like pj_basis_create. */
 int pj_basis_create_klt(pj_basis* out, int L, const double* M, double* eig_out);
 
+/* ------------------------------------------------- 2D-PCA support (Sec. V-A) */
+
+/* Mean image and centred images of a training set (eq. (22)): X holds J
+ * images of mn = m * n floats each, contiguous (device, row-major);
+ * mean[e] = (1/J) sum_j X[j mn + e] (FP32, summed in image order) and
+ * out[j mn + e] = X[j mn + e] - mean[e].  `out` may equal X.  Device pointers;
+ * asynchronous on `stream`.  Errors: PJ_ERR_ARG (null pointer), PJ_ERR_SHAPE
+ * (J or mn < 1), PJ_ERR_HIP (no device). */
+int pj_images_center(int J, int64_t mn, const float* X, float* mean, float* out, void* stream);
+
+/* out[j mn + e] = X[j mn + e] - mean[e] for T images (the test images minus
+ * the training mean image, before their features Y = (B - mean) X of eq.
+ * (24)).  Errors as pj_images_center. */
+int pj_images_subtract(int T, int64_t mn, const float* X, const float* mean, float* out, void* stream);
+
+/* G <- (G + G^T) / 2 in place for an n x n device matrix with row stride ld:
+ * the image scatter matrix of eq. (23) is a Gram matrix, symmetric up to the
+ * rounding of its projected product; the eigensolver takes the symmetric
+ * part.  Errors: PJ_ERR_ARG (null G), PJ_ERR_SHAPE (n < 1, ld < n). */
+int pj_symmetrize(int n, float* G, int64_t ld, void* stream);
+
+/* Squared Frobenius distances between feature matrices (eq. (25), (26)):
+ * out[i * ldo + j] = sum_{e < d} (F[i * ldf + e] - Y[j * ldy + e])^2 for the T
+ * test and J training features flattened to d values each (device, FP32
+ * accumulation per lane, lanes combined pairwise).  Errors: PJ_ERR_ARG (null
+ * pointer), PJ_ERR_SHAPE (sizes < 1 or strides too small). */
+int pj_sq_distances(int T, int J, int64_t d, const float* F, int64_t ldf, const float* Y, int64_t ldy,
+                    float* out, int64_t ldo, void* stream);
+
 /* Eigen-decomposition of a symmetric n x n matrix on the host (the same FP64
  * cyclic Jacobi rotations): w[l] are the eigenvalues in decreasing order and
  * column l of V (row-major n x n) the matching unit eigenvector, its largest-

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libprojgemm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "pack.hip", "gemm.hip", "conv.hip", "corr.hip", "fft.hip", "expand.hip", "moments.hip"]
+SOURCES = ["api.cpp", "pack.hip", "gemm.hip", "conv.hip", "corr.hip", "fft.hip", "expand.hip", "moments.hip",
+           "pca2d.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-x", "hip",

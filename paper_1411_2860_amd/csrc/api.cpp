@@ -14,6 +14,7 @@
 #include "common.h"
 #include "conv.h"
 #include "moments.h"
+#include "pca2d.h"
 
 using namespace pj;
 
@@ -1170,6 +1171,42 @@ int pj_block_moments(int L, int64_t rows, int64_t K, const float* X, int64_t ld,
     if (g.ws_bytes > 0 && (!ws || ws_bytes < (size_t)g.ws_bytes)) return PJ_ERR_WORKSPACE;
     if (!device_present()) return PJ_ERR_HIP;
     return launch_moments(X, ld, rows, K, L, M, ws, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
+}
+
+int pj_images_center(int J, int64_t mn, const float* X, float* mean, float* out, void* stream)
+{
+    if (!X || !mean || !out) return PJ_ERR_ARG;
+    if (J < 1 || mn < 1) return PJ_ERR_SHAPE;
+    if (!device_present()) return PJ_ERR_HIP;
+    const int rc = launch_center(J, mn, X, mean, out, false, (hipStream_t)stream);
+    return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
+}
+
+int pj_images_subtract(int T, int64_t mn, const float* X, const float* mean, float* out, void* stream)
+{
+    if (!X || !mean || !out) return PJ_ERR_ARG;
+    if (T < 1 || mn < 1) return PJ_ERR_SHAPE;
+    if (!device_present()) return PJ_ERR_HIP;
+    const int rc = launch_center(T, mn, X, const_cast<float*>(mean), out, true, (hipStream_t)stream);
+    return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
+}
+
+int pj_symmetrize(int n, float* G, int64_t ld, void* stream)
+{
+    if (!G) return PJ_ERR_ARG;
+    if (n < 1 || n > 65535 * 16 || ld < n) return PJ_ERR_SHAPE;
+    if (!device_present()) return PJ_ERR_HIP;
+    return launch_symmetrize(n, G, ld, (hipStream_t)stream) == 0 ? PJ_OK : PJ_ERR_HIP;
+}
+
+int pj_sq_distances(int T, int J, int64_t d, const float* F, int64_t ldf, const float* Y, int64_t ldy, float* out,
+                    int64_t ldo, void* stream)
+{
+    if (!F || !Y || !out) return PJ_ERR_ARG;
+    if (T < 1 || J < 1 || d < 1 || ldf < d || ldy < d || ldo < J) return PJ_ERR_SHAPE;
+    if (!device_present()) return PJ_ERR_HIP;
+    const int rc = launch_sqdist(T, J, d, F, ldf, Y, ldy, out, ldo, (hipStream_t)stream);
+    return rc == 0 ? PJ_OK : (rc == -2 ? PJ_ERR_UNSUPPORTED : PJ_ERR_HIP);
 }
 
 int pj_sym_eig(int n, const double* A, double* w, double* V)

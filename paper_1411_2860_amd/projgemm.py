@@ -19,7 +19,7 @@ __all__ = [
     "conv1d", "conv1d_workspace_bytes", "conv1d_fft", "conv1d_fft_workspace_bytes", "conv1d_method",
     "conv1d_method_workspace_bytes", "gemm_backward", "gemm_save", "gemm_saved_bytes",
     "gemm_backward_saved", "GemmDesc", "gemm_batched", "gemm_batched_workspace_bytes",
-    "status_str",
+    "images_center", "images_subtract", "symmetrize", "sq_distances", "status_str",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -75,6 +75,10 @@ _SIGNATURES = {
     "pj_gemm_backward_workspace_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
     "proj_gemm_backward": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                                 _i64, _i, _vp, _sz, _vp]),
+    "pj_images_center": (_i, [_i, _i64, _vp, _vp, _vp, _vp]),
+    "pj_images_subtract": (_i, [_i, _i64, _vp, _vp, _vp, _vp]),
+    "pj_symmetrize": (_i, [_i, _vp, _i64, _vp]),
+    "pj_sq_distances": (_i, [_i, _i, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "pj_gemm_saved_bytes": (_sz, [_i, _i, _i, _i, _i, _i]),
     "proj_gemm_save": (_i, [_vp, _i, _ch, _ch, _i, _i, _i, _vp, _i64, _vp, _i64, _f, _vp, _i64, _i, _vp, _sz, _vp,
                             _sz, _vp]),
@@ -209,6 +213,58 @@ def klt_basis(M):
            "pj_basis_create_klt")
     b.kind, b.L = "klt", L
     return b, eig
+
+
+def images_center(X, out=None, stream=None):
+    """(mean, centred) of J images X (CUDA float32, J x m x n, contiguous):
+    mean over the images and every image minus it (pj_images_center)."""
+    import torch
+    if X.dtype != torch.float32 or not X.is_contiguous():
+        raise TypeError("X must be a contiguous float32 tensor")
+    J = X.shape[0]
+    mn = X[0].numel()
+    mean = torch.empty(X.shape[1:], dtype=torch.float32, device=X.device)
+    if out is None:
+        out = torch.empty_like(X)
+    _check(lib().pj_images_center(J, mn, _ptr(X), _ptr(mean), _ptr(out), _stream(stream)), "pj_images_center")
+    return mean, out
+
+
+def images_subtract(X, mean, out=None, stream=None):
+    """X minus the image `mean` for T images X (CUDA float32, T x m x n,
+    contiguous; pj_images_subtract)."""
+    import torch
+    if X.dtype != torch.float32 or not X.is_contiguous() or not mean.is_contiguous():
+        raise TypeError("X and mean must be contiguous float32 tensors")
+    if out is None:
+        out = torch.empty_like(X)
+    _check(lib().pj_images_subtract(X.shape[0], X[0].numel(), _ptr(X), _ptr(mean), _ptr(out), _stream(stream)),
+           "pj_images_subtract")
+    return out
+
+
+def symmetrize(G, stream=None):
+    """G <- (G + G^T) / 2 in place (CUDA float32 square matrix, pj_symmetrize)."""
+    n = G.shape[0]
+    if G.shape != (n, n) or G.stride(1) != 1:
+        raise ValueError("G must be square with unit column stride")
+    _check(lib().pj_symmetrize(n, _ptr(G), G.stride(0), _stream(stream)), "pj_symmetrize")
+    return G
+
+
+def sq_distances(F, Y, out=None, stream=None):
+    """out[i, j] = ||F_i - Y_j||^2 for the rows of F (T x d) and Y (J x d),
+    CUDA float32 (pj_sq_distances)."""
+    import torch
+    T, d = F.shape
+    J, d2 = Y.shape
+    if d2 != d or F.stride(1) != 1 or Y.stride(1) != 1:
+        raise ValueError("F and Y need the same row length and unit column stride")
+    if out is None:
+        out = torch.empty((T, J), dtype=torch.float32, device=F.device)
+    _check(lib().pj_sq_distances(T, J, d, _ptr(F), F.stride(0), _ptr(Y), Y.stride(0), _ptr(out), out.stride(0),
+                                 _stream(stream)), "pj_sq_distances")
+    return out
 
 
 def sym_eig(A):

@@ -216,6 +216,24 @@ def test_batched_tiles_workspace(lib):
                                        FAKE, ws, None) == ARG
 
 
+def test_pca2d_support_validation(lib):
+    """Centring, symmetrisation and distance entry points reject bad
+    arguments before any device work; valid calls need a device."""
+    assert lib.pj_images_center(3, 16, None, FAKE, FAKE, None) == ARG
+    assert lib.pj_images_center(0, 16, FAKE, FAKE, FAKE, None) == SHAPE
+    assert lib.pj_images_subtract(2, 16, FAKE, None, FAKE, None) == ARG
+    assert lib.pj_images_subtract(2, 0, FAKE, FAKE, FAKE, None) == SHAPE
+    assert lib.pj_symmetrize(4, None, 4, None) == ARG
+    assert lib.pj_symmetrize(4, FAKE, 3, None) == SHAPE
+    assert lib.pj_sq_distances(2, 3, 10, FAKE, 10, None, 10, FAKE, 3, None) == ARG
+    assert lib.pj_sq_distances(2, 3, 10, FAKE, 9, FAKE, 10, FAKE, 3, None) == SHAPE
+    assert lib.pj_sq_distances(2, 3, 10, FAKE, 10, FAKE, 10, FAKE, 2, None) == SHAPE
+    import torch
+    if not torch.cuda.is_available():
+        assert lib.pj_images_center(3, 16, FAKE, FAKE, FAKE, None) == HIP
+        assert lib.pj_sq_distances(2, 3, 10, FAKE, 10, FAKE, 10, FAKE, 3, None) == HIP
+
+
 def test_noalloc_validation_and_scratch_limit(lib, basis16):
     """proj_gemm_noalloc rejects what proj_gemm rejects, and a request whose
     workspace exceeds the fixed scratch, before any device work."""

@@ -80,3 +80,41 @@ def test_pipeline_full_size_yale_a_shape(pg):
     dm = ref["dist"][np.arange(gm.size), gm]
     assert np.all(dm <= ref["dist"].min(1) + 1e-3 * scale)
     np.testing.assert_allclose(model.eig[:10], ref["eig"][:10], rtol=1e-4)
+
+
+def test_support_kernels(pg):
+    """The non-GEMM steps against their definitions: mean image and centred
+    images (eq. (22)) within the FP32 summation bound, the symmetric part of
+    G (exact: one FP32 add and halving), squared distances of eq. (25) within
+    the FP32 accumulation bound."""
+    rng = np.random.default_rng(81)
+    J, m, n = 7, 33, 29
+    X = (rng.random((J, m, n)) * 255).astype(np.float32)
+    mean, Xc = pg.images_center(torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    X64 = X.astype(np.float64)
+    u = 2.0 ** -24
+    mref = X64.mean(0)
+    _tol.assert_within(mean.double().cpu().numpy(), mref, 2 * J * u * np.abs(X64).sum(0) / J + 1e-300, "mean")
+    _tol.assert_within(Xc.double().cpu().numpy(), X64 - mref, 2 * J * u * np.abs(X64).sum(0) / J + 2 * u * np.abs(X64)
+                       + 1e-300, "centred")
+    T = 3
+    Bt = (rng.random((T, m, n)) * 255).astype(np.float32)
+    Bc = pg.images_subtract(torch.from_numpy(Bt).cuda(), mean)
+    torch.cuda.synchronize()
+    assert np.array_equal(Bc.cpu().numpy(), Bt - mean.cpu().numpy()), "B - mean is one FP32 subtraction"
+    G = rng.standard_normal((45, 45)).astype(np.float32)
+    Gd = torch.from_numpy(G).cuda()
+    pg.symmetrize(Gd)
+    torch.cuda.synchronize()
+    Gs = ((G + G.T) * np.float32(0.5)).astype(np.float32)
+    assert np.array_equal(Gd.cpu().numpy(), Gs)
+    d = 1000
+    F = rng.standard_normal((5, d)).astype(np.float32)
+    Y = rng.standard_normal((6, d)).astype(np.float32)
+    D = pg.sq_distances(torch.from_numpy(F).cuda(), torch.from_numpy(Y).cuda())
+    torch.cuda.synchronize()
+    diff = F.astype(np.float64)[:, None, :] - Y.astype(np.float64)[None, :, :]
+    ref = (diff ** 2).sum(-1)
+    bound = (d / 64 + 6 + 3) * u * 1.01 * ref + 1e-300
+    _tol.assert_within(D.double().cpu().numpy(), ref, 4 * bound, "squared distances")
