@@ -78,6 +78,83 @@ __device__ __forceinline__ f32x4 sig_chunk(const float* __restrict__ s, int64_t 
     return v;
 }
 
+// The same projection for a few projections (r <= 4; at 8 the shuffles cost
+// more than the strided tile below) and L a power of two
+// in 4 .. 256: one 16-byte chunk per lane covers 256 consecutive samples per
+// wave step, i.e. 256 / L whole blocks; lane j holds samples (4j mod L) ..
+// +3 of its block, multiplies them with its 4 x R coefficients (the same in
+// every step, loaded once), and the L / 4 lanes of a block combine their
+// partial sums with xor shuffles.  Each wave takes steps wave, wave + nwaves,
+// ... with the loads PD steps ahead; every load is unconditional (past the
+// signal: a valid address, the values masked), so the wait counts stay
+// exact.  The chunk that straddles the end of a signal whose length is not a
+// multiple of 4 is read as zeros here; sig_tail_kernel recomputes that block.
+constexpr int kFewPD = 4;
+template <int R>
+__global__ __launch_bounds__(256) void sig_project_few_kernel(const float* __restrict__ s, int64_t W, int L, int r,
+                                                              const float* __restrict__ C, float* __restrict__ sc,
+                                                              int64_t nbp, int64_t nstep)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int t = (4 * lane) & (L - 1);
+    const int lg = L / 4;                        // lanes per block
+    const int bpi = 256 / L;                     // blocks per step
+    float c[4][R];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int l = 0; l < R; ++l) c[q][l] = l < r ? C[(int64_t)(t + q) * L + l] : 0.0f;
+    const int64_t nk = wave < nstep ? (nstep - wave + nwaves - 1) / nwaves : 0;   // this wave's steps
+    auto load = [&](int64_t k) -> f32x4 {
+        const int64_t e = (wave + k * nwaves) * 256 + 4 * lane;
+        const bool full = k < nk && e + 3 < W;
+        const f32x4 v = *reinterpret_cast<const f32x4*>(s + (full ? e : 0));
+        return full ? v : f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+    f32x4 ring[kFewPD];
+#pragma unroll
+    for (int d = 0; d < kFewPD; ++d) ring[d] = load(d);
+    for (int64_t k0 = 0; k0 < nk; k0 += kFewPD) {
+#pragma unroll
+        for (int d = 0; d < kFewPD; ++d) {
+            const int64_t k = k0 + d;
+            const f32x4 x = ring[d];
+            ring[d] = load(k + kFewPD);
+            float p[R];
+#pragma unroll
+            for (int l = 0; l < R; ++l) p[l] = x[0] * c[0][l] + x[1] * c[1][l] + x[2] * c[2][l] + x[3] * c[3][l];
+            for (int off = lg / 2; off > 0; off >>= 1)
+#pragma unroll
+                for (int l = 0; l < R; ++l) p[l] += __shfl_xor(p[l], off, 64);
+            const int64_t blk = (wave + k * nwaves) * bpi + lane / lg;
+            if (k < nk && (lane & (lg - 1)) == 0 && blk < nbp) {
+#pragma unroll
+                for (int l = 0; l < R; ++l)
+                    if (l < r) sc[(int64_t)l * nbp + blk] = p[l];
+            }
+        }
+    }
+}
+
+// Block (W - 1) / L recomputed from all its samples (zeros past W), for a
+// signal whose last 16-byte chunk sig_project_few_kernel read as zeros.
+__global__ __launch_bounds__(64) void sig_tail_kernel(const float* __restrict__ s, int64_t W, int L, int r,
+                                                      const float* __restrict__ C, float* __restrict__ sc,
+                                                      int64_t nbp)
+{
+    const int64_t blk = (W - 1) / L;
+    const int l = threadIdx.x;
+    if (l >= r || blk >= nbp) return;
+    float acc = 0.0f;
+    for (int t = 0; t < L; ++t) {
+        const int64_t n = blk * L + t;
+        if (n < W) acc += s[n] * C[(int64_t)t * L + l];
+    }
+    sc[(int64_t)l * nbp + blk] = acc;
+}
+
 template <int NW, bool VEC>
 __global__ __launch_bounds__(64 * NW) void sig_project_kernel(
     const float* __restrict__ s, int64_t W, int L, int r, const float* __restrict__ C,
@@ -436,8 +513,29 @@ int launch_conv_signal_rows(const ConvArgs& a, float* sc, int64_t nbp, hipStream
 static int launch_sig_project(const ConvArgs& a, float* sc, int64_t nbp, hipStream_t st)
 {
     if (a.L > kMaxConvL) return -2;
-    dim3 grid((unsigned)cdiv(nbp, 128), (unsigned)cdiv(a.r, 32));
     const bool vec = a.L % 4 == 0 && ((uintptr_t)a.s % 16) == 0;
+    if (vec && a.r <= 4 && a.L >= 4 && (a.L & (a.L - 1)) == 0) {
+        // few projections: coalesced 16-byte chunks, partial sums combined
+        // across the lanes of a block (the 32 x 32 MFMA tile below reads the
+        // blocks strided and leaves most of the chip idle at this size)
+        const int64_t nstep = cdiv(nbp * a.L, 256);
+        const int64_t grid = std::max<int64_t>(1, cdiv(nstep, 4 * kFewPD));
+        if (grid > 0x7fffffff) return -2;
+#define PJ_FEW(R_)                                                                                              \
+    hipLaunchKernelGGL((sig_project_few_kernel<R_>), dim3((unsigned)grid), dim3(256), 0, st, a.s, a.W, a.L, a.r, \
+                       a.C, sc, nbp, nstep)
+        if (a.r == 1) PJ_FEW(1);
+        else if (a.r == 2) PJ_FEW(2);
+        else PJ_FEW(4);
+#undef PJ_FEW
+        if (hipGetLastError() != hipSuccess) return -1;
+        if (a.W % 4 != 0) {
+            hipLaunchKernelGGL(sig_tail_kernel, dim3(1), dim3(64), 0, st, a.s, a.W, a.L, a.r, a.C, sc, nbp);
+            if (hipGetLastError() != hipSuccess) return -1;
+        }
+        return 0;
+    }
+    dim3 grid((unsigned)cdiv(nbp, 128), (unsigned)cdiv(a.r, 32));
     if (vec)
         hipLaunchKernelGGL((sig_project_kernel<4, true>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, nbp);
     else

@@ -85,6 +85,20 @@ def test_ragged(pg, W, N, L, kind):
         _check(pg, s, k, kind, L, r)
 
 
+@pytest.mark.parametrize("L", [16, 32, 64, 128, 256])
+def test_few_projection_signal_pass(pg, L):
+    """r <= 4 with L a power of two: the signal projection reads 256-sample
+    steps across lanes (several blocks per step below L = 256) and the block
+    holding a ragged tail (W not a multiple of 4) is recomputed from its
+    samples; full and block rate."""
+    rng = np.random.default_rng(L)
+    for W in (20 * L + 3, 20 * L + 4, 7 * L + 1):
+        s, k = rng.standard_normal(W), rng.standard_normal(3 * L + 1)
+        for r in (1, 3, 4, 8):
+            _check(pg, s, k, "dct2", L, r)
+            _check_block(pg, s, k, "dct2", L, r)
+
+
 @pytest.mark.parametrize("r", [7, 33])
 def test_half_kblock_phases(pg, r):
     """12 kernel blocks per projection (N = 500, L = 64): every k-block of 8
