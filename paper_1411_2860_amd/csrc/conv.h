@@ -17,6 +17,7 @@ struct ConvGeom {
     int64_t tiles_n;   // column tiles (phases b)
     int nsplit;        // contiguous projection ranges contracted by separate workgroups
     bool small;        // L <= kSmallL: vector-ALU path (kernel phases in plain layout)
+    bool half_m;       // row tile halved (too few tiles for the chip otherwise)
     int64_t sc_bytes, k_bytes, part_bytes, total;
 };
 ConvGeom conv_geom(int64_t W, int64_t N, int L, int r);

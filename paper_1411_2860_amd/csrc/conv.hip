@@ -478,19 +478,24 @@ ConvGeom conv_geom(int64_t W, int64_t N, int L, int r)
     g.nc = (N + L - 2) / L + 1;
     g.ncp = rup(g.nc, 4);
     g.rows = cdiv(g.nout, L);                       // output rows a
-    const int bm = xcorr_bm(L);
-    g.tiles_m = cdiv(g.rows, bm);
-    g.nbp = rup(g.tiles_m * bm + g.ncp, 64);        // projected-signal row length
     g.k_nrb = cdiv(L, 32);
     g.k_nkb = cdiv((int64_t)r * g.ncp, 8);
     g.tiles_n = cdiv(g.k_nrb, xcorr_bnb(L));
     g.small = L <= kSmallL;
-    const int64_t tiles = g.tiles_m * g.tiles_n;
-    const int64_t t1 = std::max<int64_t>(1, tiles);
-    const int64_t fill = std::min<int64_t>(cdiv(kXcorrFillWG, t1), g.k_nkb / kXcorrFillSteps);
-    const int64_t more = std::min<int64_t>(kXcorrTargetWG / t1, g.k_nkb / kXcorrMinSteps);
-    int64_t ns = std::max<int64_t>(1, std::max(fill, more));
-    ns = std::min<int64_t>(ns, r);
+    // row tile: halved when the grid (tiles x contraction ranges) would not
+    // give every CU a workgroup (few projections: short contractions, no split)
+    auto split_of = [&](int64_t tiles) {
+        const int64_t t1 = std::max<int64_t>(1, tiles);
+        const int64_t fill = std::min<int64_t>(cdiv(kXcorrFillWG, t1), g.k_nkb / kXcorrFillSteps);
+        const int64_t more = std::min<int64_t>(kXcorrTargetWG / t1, g.k_nkb / kXcorrMinSteps);
+        return std::min<int64_t>(std::max<int64_t>(1, std::max(fill, more)), r);
+    };
+    int bm = xcorr_bm(L);
+    g.half_m = cdiv(g.rows, bm) * g.tiles_n * split_of(cdiv(g.rows, bm) * g.tiles_n) < 256;
+    if (g.half_m) bm /= 2;
+    g.tiles_m = cdiv(g.rows, bm);
+    g.nbp = rup(g.tiles_m * bm + g.ncp, 64);        // projected-signal row length
+    const int64_t ns = split_of(g.tiles_m * g.tiles_n);
     g.nsplit = g.small ? 1 : (int)ns;
     if (g.small) {       // everything happens inside the workgroups (corr.hip)
         g.sc_bytes = g.k_bytes = g.part_bytes = 0;
@@ -589,18 +594,14 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
     {
         float* part = (float*)((char*)a.ws + g.sc_bytes + g.k_bytes);
         dim3 grid((unsigned)(g.tiles_m * g.tiles_n), (unsigned)g.nsplit);
-        if (a.L > 128)
-            hipLaunchKernelGGL((xcorr_kernel<2, 2, 2, 4>), grid, dim3(512), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb,
-                               g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
-        else if (a.L > 64)
-            hipLaunchKernelGGL((xcorr_kernel<2, 2, 2, 2>), grid, dim3(256), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb,
-                               g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
-        else if (a.L > 32)
-            hipLaunchKernelGGL((xcorr_kernel<2, 1, 2, 2>), grid, dim3(256), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb,
-                               g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
-        else
-            hipLaunchKernelGGL((xcorr_kernel<2, 1, 4, 1>), grid, dim3(256), 0, st, sc, g.nbp, kp, g.k_nrb, g.k_nkb,
-                               g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m);
+#define PJ_XC(WM_, WN_, WA_, WB_)                                                                                 \
+    hipLaunchKernelGGL((xcorr_kernel<WM_, WN_, WA_, WB_>), grid, dim3(64 * WA_ * WB_), 0, st, sc, g.nbp, kp,      \
+                       g.k_nrb, g.k_nkb, g.ncp, a.r, g.nsplit, a.L, g.nout, a.y, part, g.tiles_m)
+        if (a.L > 128) { if (g.half_m) PJ_XC(1, 2, 2, 4); else PJ_XC(2, 2, 2, 4); }
+        else if (a.L > 64) { if (g.half_m) PJ_XC(1, 2, 2, 2); else PJ_XC(2, 2, 2, 2); }
+        else if (a.L > 32) { if (g.half_m) PJ_XC(1, 1, 2, 2); else PJ_XC(2, 1, 2, 2); }
+        else { if (g.half_m) PJ_XC(1, 1, 4, 1); else PJ_XC(2, 1, 4, 1); }
+#undef PJ_XC
         if (hipGetLastError() != hipSuccess) return -1;
         if (g.nsplit > 1) {
             hipLaunchKernelGGL(split_sum_kernel, dim3((unsigned)cdiv(g.nout, 256)), dim3(256), 0, st, part, g.nsplit,
