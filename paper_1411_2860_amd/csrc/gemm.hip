@@ -609,9 +609,148 @@ __device__ __forceinline__ void gemm_tile_dma(
     store_tile<PREC, WM, WN>(acc, lane, rb0, cb0, P, Q, R, ldr, beta);
 }
 
+// The same copy ring with the fragments read one step ahead.  Without it,
+// each step starts with every wave of the workgroup at the barrier and then
+// waits for its LDS fragment reads before the first matrix instruction, so
+// the matrix pipe idles for a read latency per step.  Here the barrier of
+// step t makes stage t + 1 visible, its fragments are read into the second
+// register set right away, and the matrix instructions of step t (on the
+// set read during step t - 1) run while those reads are in flight.  A slot
+// is refilled right after the barrier that follows its last read, so the
+// copies still run NS - 2 stages ahead of the stage being waited for.
+template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int NS, int KS>
+__device__ __forceinline__ void gemm_tile_dma_ra(
+    const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane,
+    const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane,
+    int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
+    float beta, int64_t tm, int64_t tn)
+{
+    using T = MT<PREC>;
+    using frag = typename T::frag;
+    using acc_t = typename T::acc;
+    constexpr int PL = T::PLANES;
+    constexpr int NW = WAVES_M * WAVES_N;
+    constexpr int BMB = WM * WAVES_M, BNB = WN * WAVES_N;
+    constexpr int NTILE = (BMB + BNB) * PL;
+    constexpr int NSLOT = NTILE * KS;
+    constexpr int PER_W = (NSLOT + NW - 1) / NW;
+    constexpr int NCH = NSLOT * 64;
+    static_assert(sizeof(frag) == 16, "LDS path is for 16-byte lane formats");
+    static_assert(NSLOT % NW == 0, "every wave issues the same number of copies");
+    static_assert(NS % 2 == 0, "register sets alternate with the step parity");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    f32x4* lds = reinterpret_cast<f32x4*>(smem_raw);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+    const int64_t rbB = tm * BMB, cbB = tn * BNB;
+    const char* srcw[PER_W];
+    int kk[PER_W], slot[PER_W];
+#pragma unroll
+    for (int i = 0; i < PER_W; ++i) {
+        const int u = wave + i * NW;
+        slot[i] = u;
+        kk[i] = u / NTILE;
+        const int ti = u % NTILE;
+        const int blk = ti / PL, pl = ti % PL;
+        const int64_t base = nkb > 0 ? kb_lo : 0;
+        if (blk < BMB) {
+            const int64_t rb = rbB + blk;
+            srcw[i] = X + pl * x_plane + ((rb < x_nrb ? rb : 0) * x_nkb + base) * 1024;
+        } else {
+            const int64_t cb = cbB + blk - BMB;
+            srcw[i] = Y + pl * y_plane + ((cb < y_nrb ? cb : 0) * y_nkb + base) * 1024;
+        }
+    }
+    const int nk = (int)nkb;
+    const int nst = (nk + KS - 1) / KS;
+    // stage st holds k-blocks nk - 1 - st KS - kk (highest first); copies past
+    // k-block 0 read k-block 0 and are zeroed by fix once they have landed
+    auto copy = [&](int st, int stage) {
+#pragma unroll
+        for (int i = 0; i < PER_W; ++i) {
+            const int kb = nk - 1 - st * KS - kk[i];
+            const char* src = srcw[i] + (int64_t)(kb < 0 ? 0 : kb) * 1024 + lane * 16;
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                             reinterpret_cast<void*>(lds + stage * NCH + slot[i] * 64), 16, 0, 0);
+        }
+    };
+    auto fix = [&](int st, int stage) {
+#pragma unroll
+        for (int i = 0; i < PER_W; ++i)
+            if (nk - 1 - st * KS - kk[i] < 0) lds[stage * NCH + slot[i] * 64 + lane] = f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+
+    acc_t acc[WM][WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+#pragma unroll
+            for (int j = 0; j < T::NACC; ++j) acc[a][b][j] = 0;
+    frag fa[2][KS][WM][PL], fb[2][KS][WN][PL];
+    auto read = [&](int s, int set) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const f32x4* base = lds + s * NCH + k * NTILE * 64;
+#pragma unroll
+            for (int a = 0; a < WM; ++a)
+#pragma unroll
+                for (int pl = 0; pl < PL; ++pl)
+                    fa[set][k][a][pl] = *reinterpret_cast<const frag*>(&base[((wm * WM + a) * PL + pl) * 64 + lane]);
+#pragma unroll
+            for (int b = 0; b < WN; ++b)
+#pragma unroll
+                for (int pl = 0; pl < PL; ++pl)
+                    fb[set][k][b][pl] =
+                        *reinterpret_cast<const frag*>(&base[((BMB + wn * WN + b) * PL + pl) * 64 + lane]);
+        }
+    };
+    auto mmas = [&](int set) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+#pragma unroll
+            for (int a = 0; a < WM; ++a)
+#pragma unroll
+                for (int b = 0; b < WN; ++b) T::mma(acc[a][b], fa[set][k][a], fb[set][k][b]);
+    };
+    constexpr int AHEAD = (NS - 2) * PER_W;     // copies issued after those of the stage waited for
+    static_assert((NS - 1) * PER_W < 64, "in-flight copy count");
+#pragma unroll
+    for (int d = 0; d < NS; ++d) copy(d, d);
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"((NS - 1) * PER_W) : "memory");
+    fix(0, 0);
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    read(0, 0);
+    // step t = trip start + d: slot d, register set d & 1 holding stage t
+    auto step = [&](int t, int d) {
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(AHEAD) : "memory");   // own copies of stage t + 1
+        fix(t + 1, (d + 1) % NS);
+        // every wave's copies of stage t + 1 are in, every read of slot d is done
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        copy(t + NS, d);
+        read((d + 1) % NS, (d + 1) & 1);
+        mmas(d & 1);
+    };
+    const int nfull = nst - nst % NS;
+    for (int t0 = 0; t0 < nfull; t0 += NS) {
+#pragma unroll
+        for (int d = 0; d < NS; ++d) step(t0 + d, d);
+    }
+#pragma unroll
+    for (int d = 0; d + 1 < NS; ++d)
+        if (d < nst - nfull) step(nfull + d, d);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no copy outlives the workgroup's LDS
+
+    const int64_t rb0 = rbB + wm * WM, cb0 = cbB + wn * WN;
+    store_tile<PREC, WM, WN>(acc, lane, rb0, cb0, P, Q, R, ldr, beta);
+}
+
 // Kernel body selector: KIND 0 = direct fragment loads, 1 = LDS-staged with
 // loads two steps ahead, 2 = LDS-staged with loads four steps ahead, 3 = LDS
-// ring filled by direct global-to-LDS copies.
+// ring filled by direct global-to-LDS copies, 4 = the same ring with the
+// fragments read one step ahead.
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 __device__ __forceinline__ void gemm_any(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
@@ -619,7 +758,10 @@ __device__ __forceinline__ void gemm_any(
     int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
     float beta, int64_t tm, int64_t tn)
 {
-    if constexpr (KIND == 3 && sizeof(typename MT<PREC>::frag) == 16)
+    if constexpr (KIND == 4 && sizeof(typename MT<PREC>::frag) == 16)
+        gemm_tile_dma_ra<PREC, WM, WN, WAVES_M, WAVES_N, 4, gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>()>(
+            X, x_nrb, x_nkb, x_plane, Y, y_nrb, y_nkb, y_plane, nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
+    else if constexpr (KIND == 3 && sizeof(typename MT<PREC>::frag) == 16)
         gemm_tile_dma<PREC, WM, WN, WAVES_M, WAVES_N, 4>(X, x_nrb, x_nkb, x_plane, x_pb, Y, y_nrb, y_nkb, y_plane,
                                                          y_pb, nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
     else if constexpr (KIND >= 1 && sizeof(typename MT<PREC>::frag) == 16)
@@ -634,7 +776,7 @@ __device__ __forceinline__ void gemm_any(
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 constexpr size_t gemm_lds_bytes()
 {
-    if constexpr (KIND == 3 && sizeof(typename MT<PREC>::frag) == 16)
+    if constexpr (KIND >= 3 && sizeof(typename MT<PREC>::frag) == 16)
         return 4ull * gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>() * (WM * WAVES_M + WN * WAVES_N) *
                MT<PREC>::PLANES * 1024;
     else if constexpr (KIND >= 1 && sizeof(typename MT<PREC>::frag) == 16)
@@ -744,7 +886,7 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
 
 }  // namespace
 
-// Tile configurations: (kind: 0 direct fragment loads, 1 - 3 LDS-staged; MFMA
+// Tile configurations: (kind: 0 direct fragment loads, 1 - 4 LDS-staged; MFMA
 // blocks per wave along M, along N; waves along M, along N; minimum resident
 // workgroups per CU).  The workgroup tile is RB*WM*WAVES_M x RB*WN*WAVES_N.
 // FP8 runs the LDS kinds as direct.
@@ -764,7 +906,9 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     X(12, 3, 2, 2, 4, 2, 1)  \
     X(13, 3, 2, 2, 2, 2, 2)  \
     X(14, 3, 4, 2, 2, 2, 1)  \
-    X(15, 2, 2, 2, 4, 2, 1)
+    X(15, 2, 2, 2, 4, 2, 1)  \
+    X(16, 4, 2, 2, 4, 2, 1)  \
+    X(17, 4, 2, 2, 2, 2, 2)
 
 namespace {
 struct TileCfg { int wm, wn, wavm, wavn; };
@@ -866,16 +1010,14 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
     case P_F64: return 10;                                 // LDS, 8 waves, 128 x 64 (16 x 16 blocks)
     case P_F32:
         if (!fill256) return 0;
-        return nkb >= 256 ? 12 : 10;                       // long: LDS ring by direct copies; else LDS 8 waves
+        return nkb >= 64 ? 16 : 10;                        // long: copy ring read ahead, 256 x 128; else LDS 8 waves
     case P_FP8:
     case P_FP8X2: return 9;                                // 128 x 256, 8 waves, fragments direct
     case P_BF16X3:
     case P_F16X3:
-        if (!fill256) return 0;
-        return nkb >= 128 ? 2 : 9;                         // long: direct 128 x 256; else LDS 8 waves
-    default:                                               // BF16, FP16
+    default:                                               // BF16, FP16 and their x3 splits
         if (!fill256) return 0;                            // direct 128 x 128
-        return nkb >= 128 ? 13 : 9;                        // long: LDS ring by direct copies, 2 per CU
+        return nkb >= 64 ? 16 : 9;                         // long: copy ring read ahead, 256 x 128; else LDS 8 waves
     }
 }
 

@@ -60,7 +60,7 @@ def test_small_uneven_batch(pg, prec, r):
         _tol.assert_within(R.double().cpu().numpy(), ref, _bound(prec, A, B, C, D, r, L), f"problem {i} {prec} r={r}")
 
 
-@pytest.mark.parametrize("cfg", range(16))
+@pytest.mark.parametrize("cfg", range(18))
 def test_every_tile_config_and_layouts(pg, cfg):
     """Each workgroup tile configuration of the persistent launch, with mixed
     layouts: A stored transposed, B stored transposed."""
@@ -80,7 +80,7 @@ def test_every_tile_config_and_layouts(pg, cfg):
                                f"cfg {cfg} {prec} problem {i}")
 
 
-@pytest.mark.parametrize("cfg", [0, 6, 9, 13])
+@pytest.mark.parametrize("cfg", [0, 6, 9, 13, 16, 17])
 def test_mixed_per_problem_tiles(pg, cfg):
     """One persistent launch running some problems in the configuration's
     tile and the others in its small tile (alternating, and the library's own
