@@ -1033,7 +1033,7 @@ int proj_conv1d_fft(pj_basis b, int r, int mode, int64_t W, const float* s, int 
     const ConvFftGeom g = conv_fft_geom(W, N, b->L, r);
     if (!g.ok) return PJ_ERR_UNSUPPORTED;
     if ((int64_t)r * b->L > 0x7fffffff || (int64_t)r * g.nseg > 0x7fffffff || (int64_t)b->L * g.nseg > 0x7fffffff ||
-        cdiv(g.nseg, 2) > 65535 || cdiv(g.nbp, 128) > 0x7fffffff)
+        cdiv(g.nseg, 2) > 65535 || cdiv(g.nbp, 32) > 0x7fffffff)
         return PJ_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < (size_t)g.total) return PJ_ERR_WORKSPACE;
     if (!b->on_device) return PJ_ERR_HIP;
@@ -1098,7 +1098,7 @@ int proj_conv1d_rate(pj_basis b, int r, int mode, int rate, int64_t W, const flo
     if (W < 1 || N < 1 || N > W) return PJ_ERR_SHAPE;
     if (prec != PJ_F32) return PJ_ERR_UNSUPPORTED;
     const ConvBlockGeom g = conv_block_geom(W, N, b->L, r);
-    if (cdiv(g.nbp, 128) > 0x7fffffff || cdiv((int64_t)g.nch * g.ntp, 256) > 0x7fffffff ||
+    if (cdiv(g.nbp, 32) > 0x7fffffff || cdiv((int64_t)g.nch * g.ntp, 256) > 0x7fffffff ||
         cdiv(g.nout, 256) > 0x7fffffff || g.ntp > 0x7fffffff)
         return PJ_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < (size_t)g.total) return PJ_ERR_WORKSPACE;

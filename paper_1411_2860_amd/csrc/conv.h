@@ -105,8 +105,12 @@ struct CorrBlockArgs {
     float* y;
 };
 int launch_corr_block(const CorrBlockArgs& a, int src, hipStream_t s);
+// Kernel-side taps of the block rate (L <= 256), on aligned kernel blocks
+// c < hld, zero for c >= ncb: launch_kblock_taps writes h[l hld + c] =
+// sum_u D[l, u] k'(cL + u) for l < r; launch_ktilde writes those into kd
+// (r x hld) and then h[t hld + c] = sum_{l<r} C[t, l] kd[l hld + c] for t < L.
 int launch_ktilde(const float* k, int64_t N, int reverse, int L, int r, int64_t ncb, const float* CT, const float* DT,
-                  float* h, int64_t hld, hipStream_t s);
+                  float* kd, float* h, int64_t hld, hipStream_t s);
 int launch_kblock_taps(const float* k, int64_t N, int reverse, int L, int r, int64_t ncb, int64_t hld,
                        const float* DT, float* h, hipStream_t s);
 

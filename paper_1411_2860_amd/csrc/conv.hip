@@ -155,50 +155,85 @@ __global__ __launch_bounds__(64) void sig_tail_kernel(const float* __restrict__ 
     sc[(int64_t)l * nbp + blk] = acc;
 }
 
-template <int NW, bool VEC>
-__global__ __launch_bounds__(64 * NW) void sig_project_kernel(
+// The NW = 4 waves of a workgroup share its 32 blocks and split the
+// contraction over t: wave w takes chunks [w ncw, (w + 1) ncw) of 8 samples
+// (4 per lane half), issues every load of its range before its first matrix
+// instruction (one memory latency, and a chain of at most L / 8 matrix
+// instructions instead of L / 2), and the four partial tiles are added in LDS
+// in a fixed order (highest wave first); wave q then writes accumulator
+// registers 4q .. 4q + 3.
+constexpr int kSplitNW = 4;
+__device__ __forceinline__ f32x16 split_sum(f32x4 (*red)[4][64], const f32x16& acc, int wave, int lane)
+{
+    __syncthreads();      // the previous tile's sums have been read
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        red[wave][q][lane] = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+    __syncthreads();
+    f32x4 v = red[kSplitNW - 1][wave][lane];
+#pragma unroll
+    for (int w = kSplitNW - 2; w >= 0; --w) v += red[w][wave][lane];
+    f32x16 out;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = v[e];
+    return out;     // registers 4 wave .. 4 wave + 3 of the summed tile, in out[0 .. 3]
+}
+
+// With fewer than four chunks per block (L <= 24) the split would idle waves:
+// SPLIT = false gives each wave its own 32 blocks and the whole contraction.
+template <bool VEC, bool SPLIT>
+__global__ __launch_bounds__(64 * kSplitNW) void sig_project_kernel(
     const float* __restrict__ s, int64_t W, int L, int r, const float* __restrict__ C,
     float* __restrict__ sc, int64_t nbp)
 {
-    constexpr int PD = 8;                          // chunks in flight per lane
-    __shared__ float Cs[kMaxConvL * 32];          // [t][l - l0]
+    constexpr int MAXC = kMaxConvL / 8 / kSplitNW;   // chunks per wave
+    __shared__ float Cs[kMaxConvL * 32];              // [t][l - l0]
+    __shared__ f32x4 red[kSplitNW][4][64];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row = lane & 31, g = lane >> 5;
     const int l0 = blockIdx.y * 32;
-    const int64_t i0 = ((int64_t)blockIdx.x * NW + wave) * 32;
+    const int64_t i0 = ((int64_t)blockIdx.x * (SPLIT ? 1 : kSplitNW) + (SPLIT ? 0 : wave)) * 32;
     const int nch = (L + 7) / 8;
+    const int ncw = SPLIT ? (nch + kSplitNW - 1) / kSplitNW : nch;
+    const int cb = SPLIT ? wave * ncw : 0;
     const int64_t nb = (i0 + row) * L;
+    static_assert(SPLIT || 3 <= MAXC, "unsplit blocks have at most 3 chunks");
 
-    f32x4 ring[PD];
+    f32x4 x[MAXC];
 #pragma unroll
-    for (int j = 0; j < PD; ++j) ring[j] = j < nch ? sig_chunk<VEC>(s, W, L, nb, j, g) : f32x4{0.f, 0.f, 0.f, 0.f};
-    stage_slice<64 * NW>(C, L, r, l0, Cs);
+    for (int j = 0; j < MAXC; ++j)
+        x[j] = (j < ncw && cb + j < nch) ? sig_chunk<VEC>(s, W, L, nb, cb + j, g) : f32x4{0.f, 0.f, 0.f, 0.f};
+    stage_slice<64 * kSplitNW>(C, L, r, l0, Cs);
     __syncthreads();
 
     f32x16 acc;
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-    for (int ch0 = 0; ch0 < nch; ch0 += PD) {
 #pragma unroll
-        for (int j = 0; j < PD; ++j) {
-            const int ch = ch0 + j;
-            if (ch < nch) {
-                const f32x4 x = ring[j];
-                if (ch + PD < nch) ring[j] = sig_chunk<VEC>(s, W, L, nb, ch + PD, g);
-                const float* cp = &Cs[(8 * ch + 4 * g) * 32 + row];
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[0], x[0], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[32], x[1], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[64], x[2], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[96], x[3], acc, 0, 0, 0);
-            }
+    for (int j = 0; j < MAXC; ++j) {
+        if (j < ncw && cb + j < nch) {
+            const float* cp = &Cs[(8 * (cb + j) + 4 * g) * 32 + row];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cp[32 * e], x[j][e], acc, 0, 0, 0);
         }
     }
     const int64_t i = i0 + row;
+    if constexpr (SPLIT) {
+        const f32x16 sum = split_sum(red, acc, wave, lane);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int l = l0 + 8 * (j >> 2) + 4 * g + (j & 3);
-        if (l < r && i < nbp) sc[(int64_t)l * nbp + i] = acc[j];
+        for (int e = 0; e < 4; ++e) {
+            const int jj = 4 * wave + e;
+            const int l = l0 + 8 * (jj >> 2) + 4 * g + (jj & 3);
+            if (l < r && i < nbp) sc[(int64_t)l * nbp + i] = sum[e];
+        }
+    } else {
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int l = l0 + 8 * (jj >> 2) + 4 * g + (jj & 3);
+            if (l < r && i < nbp) sc[(int64_t)l * nbp + i] = acc[jj];
+        }
     }
 }
 
@@ -209,59 +244,79 @@ __global__ __launch_bounds__(64 * NW) void sig_project_kernel(
 // k').  Lag q is phase b = L - 1 - (e mod L) of kernel block c = e / L; the
 // result goes straight to the packed right operand (fragment order, FP32
 // tiles of 32 rows x 8): row b, contraction index l * ncp + c.
-template <int NW>
-__global__ __launch_bounds__(64 * NW) void kphase_kernel(
+// NT x 32 lags per workgroup on independent accumulators (NT = 4 with more
+// than 32 projections, where the grid has several projection tiles already
+// and the staged slice of D then serves 128 lags); its four waves split the
+// contraction over u as the signal projection above does.
+template <int NT>
+__global__ __launch_bounds__(64 * kSplitNW) void kphase_kernel(
     const float* __restrict__ k, int64_t N, int reverse, int L, int r, int64_t ncp, const float* __restrict__ DT,
     char* __restrict__ out, int64_t k_nkb)
 {
-    constexpr int QW = 32 * NW;
-    constexpr int KS = QW + kMaxConvL + 8;
+    constexpr int KS = 32 * NT + kMaxConvL + 8;
+    constexpr int KPT = (KS + 64 * kSplitNW - 1) / (64 * kSplitNW);
     __shared__ float Ds[kMaxConvL * 32];          // [u][l - l0]
     __shared__ float Ks[KS];                      // k'(qlo + x)
+    __shared__ f32x4 red[kSplitNW][4][64];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row = lane & 31, g = lane >> 5;
     const int l0 = blockIdx.y * 32;
-    const int64_t e0 = (int64_t)blockIdx.x * QW;
+    const int64_t e0 = (int64_t)blockIdx.x * 32 * NT;
     const int64_t qlo = e0 - (L - 1);
     const int nch = (L + 7) / 8;
+    const int ncw = (nch + kSplitNW - 1) / kSplitNW;
+    const int cb = wave * ncw;
 
-    stage_slice<64 * NW>(DT, L, r, l0, Ds);
-    for (int idx = tid; idx < QW + nch * 8; idx += 64 * NW) {
+    float kv[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int idx = tid + j * 64 * kSplitNW;
         const int64_t n = qlo + idx;
-        float v = 0.0f;
-        if (n >= 0 && n < N) v = reverse ? k[N - 1 - n] : k[n];
-        Ks[idx] = v;
+        kv[j] = (idx < 32 * NT + nch * 8 && n >= 0 && n < N) ? (reverse ? k[N - 1 - n] : k[n]) : 0.0f;
+    }
+    stage_slice<64 * kSplitNW>(DT, L, r, l0, Ds);
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int idx = tid + j * 64 * kSplitNW;
+        if (idx < 32 * NT + nch * 8) Ks[idx] = kv[j];
     }
     __syncthreads();
 
-    f32x16 acc;
+    f32x16 acc[NT];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-    const float* kp = Ks + wave * 32 + row;        // lane's lag, tap 0
-    for (int ch = 0; ch < nch; ++ch) {
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
+    for (int ch = cb; ch < cb + ncw && ch < nch; ++ch) {
         const float* dp = &Ds[(8 * ch + 4 * g) * 32 + row];
-        const float* hp = kp + 8 * ch + 4 * g;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[0], hp[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[32], hp[1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[64], hp[2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[96], hp[3], acc, 0, 0, 0);
-    }
-
-    const int64_t e = e0 + wave * 32 + row;
-    if (e >= ncp * L) return;
-    const int64_t c = e / L;
-    const int b = L - 1 - (int)(e - c * L);
-    const int64_t cb = b / 32;
-    const int bl = b % 32;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int l = l0 + 8 * (j >> 2) + 4 * g + (j & 3);
-        if (l >= r) continue;
-        const int64_t kk = (int64_t)l * ncp + c;
-        const int ln = bl + 32 * (int)((kk % 8) / 4);
-        const int64_t off = ((cb * k_nkb + kk / 8) * 64 + ln) * 16 + (kk % 4) * 4;
-        *reinterpret_cast<float*>(out + off) = acc[j];
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)   // lane's lag of tile t, tap 8 ch + 4 g + e
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[32 * e], Ks[32 * t + row + 8 * ch + 4 * g + e],
+                                                              acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const f32x16 sum = split_sum(red, acc[t], wave, lane);
+        const int64_t e = e0 + 32 * t + row;
+        if (e >= ncp * L) continue;
+        const int64_t c = e / L;
+        const int b = L - 1 - (int)(e - c * L);
+        const int64_t cbk = b / 32;
+        const int bl = b % 32;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jj = 4 * wave + q;
+            const int l = l0 + 8 * (jj >> 2) + 4 * g + (jj & 3);
+            if (l >= r) continue;
+            const int64_t kk = (int64_t)l * ncp + c;
+            const int ln = bl + 32 * (int)((kk % 8) / 4);
+            const int64_t off = ((cbk * k_nkb + kk / 8) * 64 + ln) * 16 + (kk % 4) * 4;
+            *reinterpret_cast<float*>(out + off) = sum[q];
+        }
     }
 }
 
@@ -540,11 +595,12 @@ static int launch_sig_project(const ConvArgs& a, float* sc, int64_t nbp, hipStre
         }
         return 0;
     }
-    dim3 grid((unsigned)cdiv(nbp, 128), (unsigned)cdiv(a.r, 32));
-    if (vec)
-        hipLaunchKernelGGL((sig_project_kernel<4, true>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, nbp);
-    else
-        hipLaunchKernelGGL((sig_project_kernel<4, false>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, nbp);
+    const bool split = (a.L + 7) / 8 >= kSplitNW;
+    dim3 grid((unsigned)cdiv(nbp, split ? 32 : 32 * kSplitNW), (unsigned)cdiv(a.r, 32));
+#define PJ_SP(V, S) hipLaunchKernelGGL((sig_project_kernel<V, S>), grid, dim3(256), 0, st, a.s, a.W, a.L, a.r, a.C, sc, nbp)
+    if (vec) { if (split) PJ_SP(true, true); else PJ_SP(true, false); }
+    else { if (split) PJ_SP(false, true); else PJ_SP(false, false); }
+#undef PJ_SP
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -585,9 +641,15 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
             hipLaunchKernelGGL(zero16_kernel, dim3((unsigned)cdiv(n16, 256)), dim3(256), 0, st, (f32x4*)kp, n16);
             if (hipGetLastError() != hipSuccess) return -1;
         }
-        dim3 grid((unsigned)cdiv(g.ncp * a.L, 128), (unsigned)cdiv(a.r, 32));
-        hipLaunchKernelGGL(kphase_kernel<4>, grid, dim3(256), 0, st, a.k, a.N, a.reverse, a.L, a.r, g.ncp, a.DT, kp,
-                           g.k_nkb);
+        // more than 32 projections: four lag tiles per workgroup share its staged slice of D
+        const int nt = a.r > 32 ? 4 : 1;
+        dim3 grid((unsigned)cdiv(g.ncp * a.L, 32 * nt), (unsigned)cdiv(a.r, 32));
+        if (nt == 4)
+            hipLaunchKernelGGL(kphase_kernel<4>, grid, dim3(256), 0, st, a.k, a.N, a.reverse, a.L, a.r, g.ncp, a.DT,
+                               kp, g.k_nkb);
+        else
+            hipLaunchKernelGGL(kphase_kernel<1>, grid, dim3(256), 0, st, a.k, a.N, a.reverse, a.L, a.r, g.ncp, a.DT,
+                               kp, g.k_nkb);
         if (hipGetLastError() != hipSuccess) return -1;
     }
     // step 3
@@ -645,7 +707,9 @@ ConvBlockGeom conv_block_geom(int64_t W, int64_t N, int L, int r)
     const int64_t tiles = cdiv(g.nd, corr_rows_per_tile());
     int64_t ns = std::min<int64_t>(cdiv(1024, tiles), g.nch / 8);
     g.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ns, 64));
-    if (!direct) g.sc_bytes = rup((int64_t)r * g.nbp * 4, 256);
+    // projected form: the projected signal rows; direct form: the projected
+    // kernel blocks the taps are rebuilt from
+    g.sc_bytes = direct ? rup((int64_t)r * g.ntp * 4, 256) : rup((int64_t)r * g.nbp * 4, 256);
     g.h_bytes = rup((int64_t)g.nch * g.ntp * 4, 256);
     g.part_bytes = rup((int64_t)g.nsplit * g.nd * 4, 256);     // per-range sums of the computed samples
     g.total = g.sc_bytes + g.h_bytes + g.part_bytes;
@@ -683,7 +747,7 @@ int launch_conv_block(const ConvArgs& a, hipStream_t st)
         c.x = sc; c.xld = g.nbp; c.xn = g.nbp;
         return launch_corr_block(c, 0, st);
     }
-    if (launch_ktilde(a.k, a.N, a.reverse, a.L, a.r, g.ncb, a.CT, a.DT, h, g.ntp, st) != 0) return -1;
+    if (launch_ktilde(a.k, a.N, a.reverse, a.L, a.r, g.ncb, a.CT, a.DT, sc, h, g.ntp, st) != 0) return -1;
     c.x = a.s; c.xld = 0; c.xn = a.W;
     return launch_corr_block(c, 1, st);
 }

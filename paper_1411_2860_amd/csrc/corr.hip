@@ -495,26 +495,143 @@ __global__ __launch_bounds__(256) void corr_interp_kernel(const float* __restric
     }
 }
 
-// Kernel-side taps of the block rate, kTapBlocks aligned kernel blocks per
-// workgroup (zero taps for blocks c >= ncb):
-//   kd_l[c] = sum_u D[l, u] k'(cL + u)
-//   mode 0: H(l, c) = kd_l[c];
-//   mode 1: H(t, c) = sum_{l<r} C[t, l] kd_l[c], the kernel blocks rebuilt
-//           from their first r projections.
-// Each sum is cut into ranges over 1024 threads (consecutive threads read
-// consecutive rows of D^T, resp. C^T), the range sums are added in a fixed
-// order.  These are small contractions whose time is memory latency, so the
-// work is spread wide and each thread keeps 8 loads in flight.
+// Kernel-side taps of the block rate, on aligned kernel blocks c < hld (zero
+// taps for blocks c >= ncb):
+//   kd_kernel:      KD(l, c) = sum_u D[l, u] k'(cL + u), l < r;
+//   rebuild_kernel: H(t, c) = sum_{l<r} C[t, l] KD(l, c), highest l first --
+//                   the kernel blocks rebuilt from their first r projections
+//                   (the raw polyphase grouping, chosen at many projections).
+// Both are small contractions (at most L r ncb products each); a workgroup
+// owns a 16 x 16 tile of outputs, stages the 16 rows of each operand in LDS
+// (zero-padded to a multiple of 4) and gives every thread one dot product,
+// read 4 terms at a time into 4 independent partial sums with the loop
+// unrolled so that the LDS reads run ahead (a plain loop waits out an LDS
+// read latency per step: 64 of them at L = 256), so the work spreads
+// over (rows / 16) x (blocks / 16) workgroups instead of queueing behind a few.
+constexpr int kTapT = 16;
+constexpr int kTapS = 256 + 4;      // LDS row stride (rows of at most 256 values)
+
+// Loads the tile's two operands (n values each, n <= 16 x 256) with every
+// load of a thread in flight before its first LDS store: one memory latency
+// for the staging instead of one per batch.
+template <typename LdA, typename StA, typename LdB, typename StB>
+__device__ __forceinline__ void stage_pair(int n, LdA lda, StA sta, LdB ldb, StB stb)
+{
+    constexpr int PT = kTapT * 256 / kCT;     // values per thread and operand
+    float va[PT], vb[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+        const int x = threadIdx.x + j * kCT;
+        va[j] = x < n ? lda(x) : 0.0f;
+        vb[j] = x < n ? ldb(x) : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+        const int x = threadIdx.x + j * kCT;
+        if (x < n) {
+            sta(x, va[j]);
+            stb(x, vb[j]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void kd_kernel(const float* __restrict__ k, int64_t N, int reverse, int L, int r,
+                                                 int64_t ncb, const float* __restrict__ DT, float* __restrict__ kd,
+                                                 int64_t hld)
+{
+    __shared__ __align__(16) float ds[kTapT * kTapS];     // ds[i][u] = D[l0 + i, u]
+    __shared__ __align__(16) float ks[kTapT * kTapS];     // ks[j][u] = k'((c0 + j) L + u)
+    const int tid = threadIdx.x;
+    const int l0 = blockIdx.y * kTapT;
+    const int64_t c0 = (int64_t)blockIdx.x * kTapT;
+    const int L4 = (L + 3) / 4 * 4;
+    // D^T rows u hold the l values contiguously: 16 consecutive threads read
+    // the tile's 16 rows of D at one u; the kernel blocks are read along u
+    stage_pair(kTapT * L4,
+               [&](int x) {
+                   const int u = x / kTapT, i = x - u * kTapT;
+                   return (l0 + i < r && u < L) ? DT[(int64_t)u * L + l0 + i] : 0.0f;
+               },
+               [&](int x, float v) {
+                   const int u = x / kTapT, i = x - u * kTapT;
+                   ds[i * kTapS + u] = v;
+               },
+               [&](int x) {
+                   const int j = x / L4, u = x - j * L4;
+                   const int64_t c = c0 + j, n = c * L + u;
+                   return (c < ncb && u < L && n < N) ? (reverse ? k[N - 1 - n] : k[n]) : 0.0f;
+               },
+               [&](int x, float v) {
+                   const int j = x / L4, u = x - j * L4;
+                   ks[j * kTapS + u] = v;
+               });
+    __syncthreads();
+    const int i = tid / kTapT, j = tid - (tid / kTapT) * kTapT;
+    const f32x4* dr = reinterpret_cast<const f32x4*>(ds + i * kTapS);
+    const f32x4* kr = reinterpret_cast<const f32x4*>(ks + j * kTapS);
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+    for (int q = 0; q < L4 / 4; ++q) {
+        const f32x4 a = dr[q], b = kr[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = fmaf(a[e], b[e], v[e]);
+    }
+    if (l0 + i < r && c0 + j < hld) kd[(int64_t)(l0 + i) * hld + c0 + j] = (v[0] + v[1]) + (v[2] + v[3]);
+}
+
+__global__ __launch_bounds__(256) void rebuild_kernel(int L, int r, const float* __restrict__ CT,
+                                                      const float* __restrict__ kd, float* __restrict__ h,
+                                                      int64_t hld)
+{
+    __shared__ __align__(16) float cs[kTapT * kTapS];     // cs[i][l] = C[t0 + i, l]
+    __shared__ __align__(16) float qs[kTapT * kTapS];     // qs[j][l] = KD(l, c0 + j)
+    const int tid = threadIdx.x;
+    const int t0 = blockIdx.y * kTapT;
+    const int64_t c0 = (int64_t)blockIdx.x * kTapT;
+    const int r4 = (r + 3) / 4 * 4;
+    stage_pair(kTapT * r4,
+               [&](int x) {
+                   const int l = x / kTapT, i = x - l * kTapT;
+                   return (t0 + i < L && l < r) ? CT[(int64_t)l * L + t0 + i] : 0.0f;
+               },
+               [&](int x, float v) {
+                   const int l = x / kTapT, i = x - l * kTapT;
+                   cs[i * kTapS + l] = v;
+               },
+               [&](int x) {
+                   const int l = x / kTapT, j = x - l * kTapT;
+                   return (c0 + j < hld && l < r) ? kd[(int64_t)l * hld + c0 + j] : 0.0f;
+               },
+               [&](int x, float v) {
+                   const int l = x / kTapT, j = x - l * kTapT;
+                   qs[j * kTapS + l] = v;
+               });
+    __syncthreads();
+    const int i = tid / kTapT, j = tid - (tid / kTapT) * kTapT;
+    const f32x4* cr = reinterpret_cast<const f32x4*>(cs + i * kTapS);
+    const f32x4* qr = reinterpret_cast<const f32x4*>(qs + j * kTapS);
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+    for (int q = r4 / 4 - 1; q >= 0; --q) {
+        const f32x4 a = cr[q], b = qr[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = fmaf(a[e], b[e], v[e]);
+    }
+    if (t0 + i < L && c0 + j < hld) h[(int64_t)(t0 + i) * hld + c0 + j] = (v[3] + v[2]) + (v[1] + v[0]);
+}
+
+// The projected kernel blocks alone for the projected grouping (few
+// projections, so a 16 x 16 tile of (l, c) would mostly idle): kTapBlocks
+// aligned blocks per workgroup of 1024 threads; thread (l, g) sums u over
+// range g of ng ranges of at least 16 terms (8 loads of D in flight), and
+// the range sums are added in a fixed order (highest range first).
 constexpr int kTapBlocks = 4;
 constexpr int kTapThreads = 1024;
-__global__ __launch_bounds__(kTapThreads) void block_taps_kernel(const float* __restrict__ k, int64_t N, int reverse,
-                                                                 int L, int r, int64_t ncb,
-                                                                 const float* __restrict__ CT,
-                                                                 const float* __restrict__ DT, float* __restrict__ h,
-                                                                 int64_t hld, int mode)
+__global__ __launch_bounds__(kTapThreads) void kd_range_kernel(const float* __restrict__ k, int64_t N, int reverse,
+                                                               int L, int r, int64_t ncb, const float* __restrict__ DT,
+                                                               float* __restrict__ h, int64_t hld)
 {
     __shared__ float kb[kTapBlocks][256];
-    __shared__ float kd[256][kTapBlocks];
     __shared__ float part[kTapThreads][kTapBlocks];
     const int tid = threadIdx.x;
     const int64_t cb0 = (int64_t)blockIdx.x * kTapBlocks;
@@ -524,69 +641,30 @@ __global__ __launch_bounds__(kTapThreads) void block_taps_kernel(const float* __
         kb[j][u] = (cb0 + j < ncb && n < N) ? (reverse ? k[N - 1 - n] : k[n]) : 0.0f;
     }
     __syncthreads();
-    // step 1: thread (l, g) sums u over range g of ng ranges
-    {
-        // ranges of at least 16 terms (a range sum per thread, then a serial sum of ng)
-        const int ng = max(1, min(kTapThreads / r, L / 16));
-        const int l = tid % r, g = tid / r;
-        float v[kTapBlocks] = {};
-        if (g < ng) {
-            const int ulo = (int)((int64_t)L * g / ng), uhi = (int)((int64_t)L * (g + 1) / ng);
-            for (int u0 = ulo; u0 < uhi; u0 += 8) {
-                float d[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) d[e] = u0 + e < uhi ? DT[(u0 + e) * L + l] : 0.0f;
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    if (u0 + e < uhi)
-#pragma unroll
-                        for (int j = 0; j < kTapBlocks; ++j) v[j] = fmaf(d[e], kb[j][u0 + e], v[j]);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kTapBlocks; ++j) part[tid][j] = v[j];
-        __syncthreads();
-        for (int x = tid; x < r * kTapBlocks; x += kTapThreads) {
-            const int ll = x / kTapBlocks, j = x - ll * kTapBlocks;
-            float sacc = 0.0f;
-            for (int gg = ng - 1; gg >= 0; --gg) sacc += part[gg * r + ll][j];
-            kd[ll][j] = sacc;
-        }
-        __syncthreads();
-    }
-    if (mode == 0) {
-        for (int x = tid; x < r * kTapBlocks; x += kTapThreads) {
-            const int l = x / kTapBlocks, j = x - l * kTapBlocks;
-            if (cb0 + j < hld) h[(int64_t)l * hld + cb0 + j] = kd[l][j];
-        }
-        return;
-    }
-    // step 2: thread (t, g) sums l over range g (highest l first)
-    const int ng = max(1, min(kTapThreads / L, r / 16));
-    const int t = tid % L, g = tid / L;
+    const int ng = max(1, min(kTapThreads / r, L / 16));
+    const int l = tid % r, g = tid / r;
     float v[kTapBlocks] = {};
     if (g < ng) {
-        const int lhi = (int)((int64_t)r * (ng - g) / ng), llo = (int)((int64_t)r * (ng - 1 - g) / ng);
-        for (int l0 = lhi - 1; l0 >= llo; l0 -= 8) {
-            float c[8];
+        const int ulo = (int)((int64_t)L * g / ng), uhi = (int)((int64_t)L * (g + 1) / ng);
+        for (int u0 = ulo; u0 < uhi; u0 += 8) {
+            float d[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) c[e] = l0 - e >= llo ? CT[(l0 - e) * L + t] : 0.0f;
+            for (int e = 0; e < 8; ++e) d[e] = u0 + e < uhi ? DT[(u0 + e) * L + l] : 0.0f;
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                if (l0 - e >= llo)
+                if (u0 + e < uhi)
 #pragma unroll
-                    for (int j = 0; j < kTapBlocks; ++j) v[j] = fmaf(c[e], kd[l0 - e][j], v[j]);
+                    for (int j = 0; j < kTapBlocks; ++j) v[j] = fmaf(d[e], kb[j][u0 + e], v[j]);
         }
     }
-    __syncthreads();
 #pragma unroll
     for (int j = 0; j < kTapBlocks; ++j) part[tid][j] = v[j];
     __syncthreads();
-    for (int x = tid; x < L * kTapBlocks; x += kTapThreads) {
-        const int tt = x / kTapBlocks, j = x - tt * kTapBlocks;
+    for (int x = tid; x < r * kTapBlocks; x += kTapThreads) {
+        const int ll = x / kTapBlocks, j = x - ll * kTapBlocks;
         float sacc = 0.0f;
-        for (int gg = 0; gg < ng; ++gg) sacc += part[gg * L + tt][j];
-        if (cb0 + j < hld) h[(int64_t)tt * hld + cb0 + j] = sacc;
+        for (int gg = ng - 1; gg >= 0; --gg) sacc += part[gg * r + ll][j];
+        if (cb0 + j < hld) h[(int64_t)ll * hld + cb0 + j] = sacc;
     }
 }
 
@@ -647,18 +725,23 @@ int launch_corr_block(const CorrBlockArgs& a, int src, hipStream_t s)
 }
 
 int launch_ktilde(const float* k, int64_t N, int reverse, int L, int r, int64_t ncb, const float* CT, const float* DT,
-                  float* h, int64_t hld, hipStream_t s)
+                  float* kd, float* h, int64_t hld, hipStream_t s)
 {
-    hipLaunchKernelGGL(block_taps_kernel, dim3((unsigned)cdiv(hld, kTapBlocks)), dim3(kTapThreads), 0, s, k, N,
-                       reverse, L, r, ncb, CT, DT, h, hld, 1);
+    if (L > kTapS - 4 || cdiv(hld, kTapT) > 0x7fffffff) return -2;
+    hipLaunchKernelGGL(kd_kernel, dim3((unsigned)cdiv(hld, kTapT), (unsigned)cdiv(r, kTapT)), dim3(256), 0, s, k, N,
+                       reverse, L, r, ncb, DT, kd, hld);
+    if (hipGetLastError() != hipSuccess) return -1;
+    hipLaunchKernelGGL(rebuild_kernel, dim3((unsigned)cdiv(hld, kTapT), (unsigned)cdiv(L, kTapT)), dim3(256), 0, s,
+                       L, r, CT, (const float*)kd, h, hld);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_kblock_taps(const float* k, int64_t N, int reverse, int L, int r, int64_t ncb, int64_t hld,
                        const float* DT, float* h, hipStream_t s)
 {
-    hipLaunchKernelGGL(block_taps_kernel, dim3((unsigned)cdiv(hld, kTapBlocks)), dim3(kTapThreads), 0, s, k, N,
-                       reverse, L, r, ncb, (const float*)nullptr, DT, h, hld, 0);
+    if (L > 256 || cdiv(hld, kTapBlocks) > 0x7fffffff) return -2;
+    hipLaunchKernelGGL(kd_range_kernel, dim3((unsigned)cdiv(hld, kTapBlocks)), dim3(kTapThreads), 0, s, k, N, reverse,
+                       L, r, ncb, DT, h, hld);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
