@@ -90,14 +90,16 @@ __device__ __forceinline__ f32x4 sig_chunk(const float* __restrict__ s, int64_t 
 // exact.  The chunk that straddles the end of a signal whose length is not a
 // multiple of 4 is read as zeros here; sig_tail_kernel recomputes that block.
 constexpr int kFewPD = 4;
+// (body of workgroup bx of nblk; a launch of its own or the first part of
+// project_pair_kernel)
 template <int R>
-__global__ __launch_bounds__(256) void sig_project_few_kernel(const float* __restrict__ s, int64_t W, int L, int r,
-                                                              const float* __restrict__ C, float* __restrict__ sc,
-                                                              int64_t nbp, int64_t nstep)
+__device__ __forceinline__ void sig_few_body(const float* __restrict__ s, int64_t W, int L, int r,
+                                             const float* __restrict__ C, float* __restrict__ sc, int64_t nbp,
+                                             int64_t nstep, int64_t bx, int64_t nblk)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t wave = bx * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = nblk * 4;
     const int t = (4 * lane) & (L - 1);
     const int lg = L / 4;                        // lanes per block
     const int bpi = 256 / L;                     // blocks per step
@@ -136,6 +138,14 @@ __global__ __launch_bounds__(256) void sig_project_few_kernel(const float* __res
             }
         }
     }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void sig_project_few_kernel(const float* __restrict__ s, int64_t W, int L, int r,
+                                                              const float* __restrict__ C, float* __restrict__ sc,
+                                                              int64_t nbp, int64_t nstep)
+{
+    sig_few_body<R>(s, W, L, r, C, sc, nbp, nstep, blockIdx.x, gridDim.x);
 }
 
 // Block (W - 1) / L recomputed from all its samples (zeros past W), for a
@@ -249,9 +259,9 @@ __global__ __launch_bounds__(64 * kSplitNW) void sig_project_kernel(
 // and the staged slice of D then serves 128 lags); its four waves split the
 // contraction over u as the signal projection above does.
 template <int NT>
-__global__ __launch_bounds__(64 * kSplitNW) void kphase_kernel(
-    const float* __restrict__ k, int64_t N, int reverse, int L, int r, int64_t ncp, const float* __restrict__ DT,
-    char* __restrict__ out, int64_t k_nkb)
+__device__ __forceinline__ void kphase_body(const float* __restrict__ k, int64_t N, int reverse, int L, int r,
+                                            int64_t ncp, const float* __restrict__ DT, char* __restrict__ out,
+                                            int64_t k_nkb, int64_t bx, int by)
 {
     constexpr int KS = 32 * NT + kMaxConvL + 8;
     constexpr int KPT = (KS + 64 * kSplitNW - 1) / (64 * kSplitNW);
@@ -262,8 +272,8 @@ __global__ __launch_bounds__(64 * kSplitNW) void kphase_kernel(
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row = lane & 31, g = lane >> 5;
-    const int l0 = blockIdx.y * 32;
-    const int64_t e0 = (int64_t)blockIdx.x * 32 * NT;
+    const int l0 = by * 32;
+    const int64_t e0 = bx * 32 * NT;
     const int64_t qlo = e0 - (L - 1);
     const int nch = (L + 7) / 8;
     const int ncw = (nch + kSplitNW - 1) / kSplitNW;
@@ -318,6 +328,33 @@ __global__ __launch_bounds__(64 * kSplitNW) void kphase_kernel(
             *reinterpret_cast<float*>(out + off) = sum[q];
         }
     }
+}
+
+template <int NT>
+__global__ __launch_bounds__(64 * kSplitNW) void kphase_kernel(
+    const float* __restrict__ k, int64_t N, int reverse, int L, int r, int64_t ncp, const float* __restrict__ DT,
+    char* __restrict__ out, int64_t k_nkb)
+{
+    kphase_body<NT>(k, N, reverse, L, r, ncp, DT, out, k_nkb, blockIdx.x, blockIdx.y);
+}
+
+// Both projections of a full-rate call with few projections in one launch:
+// workgroups [0, nsig) run the signal pass (sig_few_body), the others one
+// 32-lag tile of kernel phases each.  The two are independent and each alone
+// leaves most of the chip idle; a second stream joined by events would cost
+// more than either.
+template <int R>
+__global__ __launch_bounds__(256) void project_pair_kernel(const float* __restrict__ s, int64_t W, int L, int r,
+                                                           const float* __restrict__ C, float* __restrict__ sc,
+                                                           int64_t nbp, int64_t nstep, int64_t nsig,
+                                                           const float* __restrict__ k, int64_t N, int reverse,
+                                                           int64_t ncp, const float* __restrict__ DT,
+                                                           char* __restrict__ out, int64_t k_nkb)
+{
+    if ((int64_t)blockIdx.x < nsig)
+        sig_few_body<R>(s, W, L, r, C, sc, nbp, nstep, blockIdx.x, nsig);
+    else
+        kphase_body<1>(k, N, reverse, L, r, ncp, DT, out, k_nkb, (int64_t)blockIdx.x - nsig, 0);
 }
 
 // Zero fill (16-byte stores) of the packed kernel operand, needed when L is
@@ -570,11 +607,19 @@ int launch_conv_signal_rows(const ConvArgs& a, float* sc, int64_t nbp, hipStream
 {
     return launch_sig_project(a, sc, nbp, st);
 }
+// The signal pass of few projections (sig_project_few_kernel) applies: r <= 4,
+// L a power of two >= 4, a 16-byte aligned signal.
+static bool few_signal_pass(const ConvArgs& a)
+{
+    return a.L <= kMaxConvL && a.L % 4 == 0 && ((uintptr_t)a.s % 16) == 0 && a.r <= 4 && a.L >= 4 &&
+           (a.L & (a.L - 1)) == 0;
+}
+
 static int launch_sig_project(const ConvArgs& a, float* sc, int64_t nbp, hipStream_t st)
 {
     if (a.L > kMaxConvL) return -2;
     const bool vec = a.L % 4 == 0 && ((uintptr_t)a.s % 16) == 0;
-    if (vec && a.r <= 4 && a.L >= 4 && (a.L & (a.L - 1)) == 0) {
+    if (few_signal_pass(a)) {
         // few projections: coalesced 16-byte chunks, partial sums combined
         // across the lanes of a block (the 32 x 32 MFMA tile below reads the
         // blocks strided and leaves most of the chip idle at this size)
@@ -618,39 +663,66 @@ int launch_conv(const ConvArgs& a, hipStream_t st)
     }
     float* sc = (float*)a.ws;
     char* kp = (char*)a.ws + g.sc_bytes;
-    // step 1
-    if (a.period > 0) {
-        // periodic signal: project its W / L blocks once, then repeat them
-        ConvArgs p = a;
-        p.W = a.period;
-        const int64_t nb0 = a.period / a.L;
-        if (launch_sig_project(p, sc, g.nbp, st) != 0) return -1;
-        const int64_t n = (int64_t)a.r * (g.nbp - nb0);
-        if (n > 0) {
-            hipLaunchKernelGGL(wrap_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, sc, g.nbp, nb0, a.r);
-            if (hipGetLastError() != hipSuccess) return -1;
-        }
-    } else if (launch_sig_project(a, sc, g.nbp, st) != 0) {
-        return -1;
-    }
-    // step 2
-    {
-        if (a.L % 32 != 0 || ((int64_t)a.r * g.ncp) % 8 != 0) {
-            // padding rows b >= L, or the unused half of the last k-block
+    const bool pad_kp = a.L % 32 != 0 || ((int64_t)a.r * g.ncp) % 8 != 0;
+    if (a.period == 0 && few_signal_pass(a)) {
+        // steps 1 and 2 in one launch (project_pair_kernel)
+        if (pad_kp) {
             const int64_t n16 = g.k_nrb * g.k_nkb * 64;
             hipLaunchKernelGGL(zero16_kernel, dim3((unsigned)cdiv(n16, 256)), dim3(256), 0, st, (f32x4*)kp, n16);
             if (hipGetLastError() != hipSuccess) return -1;
         }
-        // more than 32 projections: four lag tiles per workgroup share its staged slice of D
-        const int nt = a.r > 32 ? 4 : 1;
-        dim3 grid((unsigned)cdiv(g.ncp * a.L, 32 * nt), (unsigned)cdiv(a.r, 32));
-        if (nt == 4)
-            hipLaunchKernelGGL(kphase_kernel<4>, grid, dim3(256), 0, st, a.k, a.N, a.reverse, a.L, a.r, g.ncp, a.DT,
-                               kp, g.k_nkb);
-        else
-            hipLaunchKernelGGL(kphase_kernel<1>, grid, dim3(256), 0, st, a.k, a.N, a.reverse, a.L, a.r, g.ncp, a.DT,
-                               kp, g.k_nkb);
+        const int64_t nstep = cdiv(g.nbp * a.L, 256);
+        const int64_t nsig = std::max<int64_t>(1, cdiv(nstep, 4 * kFewPD));
+        const int64_t nkph = cdiv(g.ncp * a.L, 32);
+        if (nsig + nkph > 0x7fffffff) return -2;
+#define PJ_PAIR(R_)                                                                                                  \
+    hipLaunchKernelGGL((project_pair_kernel<R_>), dim3((unsigned)(nsig + nkph)), dim3(256), 0, st, a.s, a.W, a.L, a.r, \
+                       a.C, sc, g.nbp, nstep, nsig, a.k, a.N, a.reverse, g.ncp, a.DT, kp, g.k_nkb)
+        if (a.r == 1) PJ_PAIR(1);
+        else if (a.r == 2) PJ_PAIR(2);
+        else PJ_PAIR(4);
+#undef PJ_PAIR
         if (hipGetLastError() != hipSuccess) return -1;
+        if (a.W % 4 != 0) {
+            hipLaunchKernelGGL(sig_tail_kernel, dim3(1), dim3(64), 0, st, a.s, a.W, a.L, a.r, a.C, sc, g.nbp);
+            if (hipGetLastError() != hipSuccess) return -1;
+        }
+    } else {
+        // step 1
+        if (a.period > 0) {
+            // periodic signal: project its W / L blocks once, then repeat them
+            ConvArgs p = a;
+            p.W = a.period;
+            const int64_t nb0 = a.period / a.L;
+            if (launch_sig_project(p, sc, g.nbp, st) != 0) return -1;
+            const int64_t n = (int64_t)a.r * (g.nbp - nb0);
+            if (n > 0) {
+                hipLaunchKernelGGL(wrap_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, sc, g.nbp, nb0, a.r);
+                if (hipGetLastError() != hipSuccess) return -1;
+            }
+        } else if (launch_sig_project(a, sc, g.nbp, st) != 0) {
+            return -1;
+        }
+        // step 2
+        {
+            if (pad_kp) {
+                // padding rows b >= L, or the unused half of the last k-block
+                const int64_t n16 = g.k_nrb * g.k_nkb * 64;
+                hipLaunchKernelGGL(zero16_kernel, dim3((unsigned)cdiv(n16, 256)), dim3(256), 0, st, (f32x4*)kp,
+                                   n16);
+                if (hipGetLastError() != hipSuccess) return -1;
+            }
+            // more than 32 projections: four lag tiles per workgroup share its staged slice of D
+            const int nt = a.r > 32 ? 4 : 1;
+            dim3 grid((unsigned)cdiv(g.ncp * a.L, 32 * nt), (unsigned)cdiv(a.r, 32));
+            if (nt == 4)
+                hipLaunchKernelGGL(kphase_kernel<4>, grid, dim3(256), 0, st, a.k, a.N, a.reverse, a.L, a.r, g.ncp,
+                                   a.DT, kp, g.k_nkb);
+            else
+                hipLaunchKernelGGL(kphase_kernel<1>, grid, dim3(256), 0, st, a.k, a.N, a.reverse, a.L, a.r, g.ncp,
+                                   a.DT, kp, g.k_nkb);
+            if (hipGetLastError() != hipSuccess) return -1;
+        }
     }
     // step 3
     {
