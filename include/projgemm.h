@@ -287,6 +287,9 @@ size_t pj_gemm_batched_workspace_bytes(int count, const pj_gemm_desc* problems, 
  *              the autotuner picks it per batch.
  * The problem and item tables (a few KB) are copied into the workspace with
  * hipMemcpyAsync from host memory; the call returns once they are staged.
+ * That copy reads host memory the call owns, so the batched calls are not for
+ * stream capture (proj_gemm, proj_gemm_noalloc and proj_conv1d enqueue
+ * kernels only and are).
  * Errors: any invalid descriptor rejects the whole batch before device work. */
 int proj_gemm_batched(pj_basis b, int r, int count, const pj_gemm_desc* problems, float beta, int prec,
                       int tile_cfg, void* ws, size_t ws_bytes, void* stream);
