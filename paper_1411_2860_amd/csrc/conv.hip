@@ -258,14 +258,18 @@ __global__ __launch_bounds__(64 * kSplitNW) void sig_project_kernel(
 // than 32 projections, where the grid has several projection tiles already
 // and the staged slice of D then serves 128 lags); its four waves split the
 // contraction over u as the signal projection above does.
-template <int NT>
+// LC = columns of D staged: 32 (a whole projection tile), or 4 when r <= 4
+// (the matrix rows l >= 4 then read zeros from registers, and the LDS of the
+// workgroup shrinks from 50 KB to 22 KB).
+template <int NT, int LC>
 __device__ __forceinline__ void kphase_body(const float* __restrict__ k, int64_t N, int reverse, int L, int r,
                                             int64_t ncp, const float* __restrict__ DT, char* __restrict__ out,
                                             int64_t k_nkb, int64_t bx, int by)
 {
     constexpr int KS = 32 * NT + kMaxConvL + 8;
     constexpr int KPT = (KS + 64 * kSplitNW - 1) / (64 * kSplitNW);
-    __shared__ float Ds[kMaxConvL * 32];          // [u][l - l0]
+    static_assert(LC == 32 || LC == 4, "staged columns of D");
+    __shared__ float Ds[kMaxConvL * LC];          // [u][l - l0], l - l0 < LC
     __shared__ float Ks[KS];                      // k'(qlo + x)
     __shared__ f32x4 red[kSplitNW][4][64];
     const int tid = threadIdx.x;
@@ -286,7 +290,23 @@ __device__ __forceinline__ void kphase_body(const float* __restrict__ k, int64_t
         const int64_t n = qlo + idx;
         kv[j] = (idx < 32 * NT + nch * 8 && n >= 0 && n < N) ? (reverse ? k[N - 1 - n] : k[n]) : 0.0f;
     }
-    stage_slice<64 * kSplitNW>(DT, L, r, l0, Ds);
+    if constexpr (LC == 32) {
+        stage_slice<64 * kSplitNW>(DT, L, r, l0, Ds);
+    } else {
+        constexpr int SPT = kMaxConvL * LC / (64 * kSplitNW);
+        float v[SPT];
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            const int idx = tid + j * 64 * kSplitNW;
+            const int t = idx / LC, l = idx % LC;
+            v[j] = (t < L && l0 + l < r) ? DT[(int64_t)t * L + l0 + l] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            const int idx = tid + j * 64 * kSplitNW;
+            if (idx < nch * 8 * LC) Ds[idx] = v[j];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
         const int idx = tid + j * 64 * kSplitNW;
@@ -300,13 +320,15 @@ __device__ __forceinline__ void kphase_body(const float* __restrict__ k, int64_t
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
     for (int ch = cb; ch < cb + ncw && ch < nch; ++ch) {
-        const float* dp = &Ds[(8 * ch + 4 * g) * 32 + row];
+        const float* dp = &Ds[(8 * ch + 4 * g) * LC + (LC == 32 ? row : (row & (LC - 1)))];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 4; ++e) {
+            const float a = (LC == 32 || row < LC) ? dp[LC * e] : 0.0f;
 #pragma unroll
             for (int t = 0; t < NT; ++t)   // lane's lag of tile t, tap 8 ch + 4 g + e
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(dp[32 * e], Ks[32 * t + row + 8 * ch + 4 * g + e],
-                                                              acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Ks[32 * t + row + 8 * ch + 4 * g + e], acc[t], 0,
+                                                              0, 0);
+        }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -335,7 +357,7 @@ __global__ __launch_bounds__(64 * kSplitNW) void kphase_kernel(
     const float* __restrict__ k, int64_t N, int reverse, int L, int r, int64_t ncp, const float* __restrict__ DT,
     char* __restrict__ out, int64_t k_nkb)
 {
-    kphase_body<NT>(k, N, reverse, L, r, ncp, DT, out, k_nkb, blockIdx.x, blockIdx.y);
+    kphase_body<NT, 32>(k, N, reverse, L, r, ncp, DT, out, k_nkb, blockIdx.x, blockIdx.y);
 }
 
 // Both projections of a full-rate call with few projections in one launch:
@@ -354,7 +376,7 @@ __global__ __launch_bounds__(256) void project_pair_kernel(const float* __restri
     if ((int64_t)blockIdx.x < nsig)
         sig_few_body<R>(s, W, L, r, C, sc, nbp, nstep, blockIdx.x, nsig);
     else
-        kphase_body<1>(k, N, reverse, L, r, ncp, DT, out, k_nkb, (int64_t)blockIdx.x - nsig, 0);
+        kphase_body<1, 4>(k, N, reverse, L, r, ncp, DT, out, k_nkb, (int64_t)blockIdx.x - nsig, 0);
 }
 
 // Zero fill (16-byte stores) of the packed kernel operand, needed when L is
