@@ -139,14 +139,18 @@ def batch64():
     return shapes, As, Bs
 
 
-@pytest.mark.parametrize("prec,r", [("bf16x3", 4), ("bf16", 16), ("fp8", 8), ("f16x3", 1)])
-def test_batch64_sampled(pg, batch64, prec, r):
+@pytest.mark.parametrize("prec,r,cfg", [("bf16x3", 4, -1), ("bf16", 16, -1), ("fp8", 8, -1), ("f16x3", 1, -1),
+                                         ("bf16x3", 4, 16), ("bf16", 16, 16), ("bf16x3", 1, 17)])
+def test_batch64_sampled(pg, batch64, prec, r, cfg):
+    """The 64-problem workload, sampled outputs of every problem, in the
+    library's default tile and in the tiles the autotuner picks for the
+    timed run."""
     shapes, As, Bs = batch64
     L = 16
     basis = pg.Basis("dct2", L)
     C, D = _ref.oracle_basis("dct2", L)
     outs = pg.gemm_batched([torch.from_numpy(a).cuda() for a in As], [torch.from_numpy(b).cuda() for b in Bs],
-                           r, basis, prec=prec)
+                           r, basis, prec=prec, tile_cfg=cfg)
     torch.cuda.synchronize()
     rng = np.random.default_rng(r)
     for i, ((m, w, k), A, B, R) in enumerate(zip(shapes, As, Bs, outs)):
@@ -157,4 +161,4 @@ def test_batch64_sampled(pg, batch64, prec, r):
         ref = oracle.gemm_proj_block(A64, B64, C, D, r, rows, cols)
         mag = oracle.gemm_proj_block(np.abs(A64), np.abs(B64), np.abs(C), np.abs(D), r, rows, cols)
         bound = _bound(prec, A64[rows], B64[:, cols], C, D, r, L, mag=mag)
-        _tol.assert_within(got, ref, bound, f"batch64 problem {i} {(m, w, k)} {prec} r={r}")
+        _tol.assert_within(got, ref, bound, f"batch64 problem {i} {(m, w, k)} {prec} r={r} cfg={cfg}")
