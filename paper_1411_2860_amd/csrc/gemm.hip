@@ -32,7 +32,9 @@ __device__ __forceinline__ F load_plain(const char* plane, int64_t plane_bytes, 
 }
 
 template <> struct MT<P_F32> {
-    static constexpr int RB = 32, NACC = 16, PLANES = 1;
+    // NMMA: matrix instructions per mma() (16-byte lane formats, for the
+    // LDS ring's instruction schedule)
+    static constexpr int RB = 32, NACC = 16, PLANES = 1, NMMA = 4;
     using frag = f32x4;
     using acc = f32x16;
     using out_t = float;
@@ -47,7 +49,7 @@ template <> struct MT<P_F32> {
 };
 
 template <> struct MT<P_F64> {
-    static constexpr int RB = 16, NACC = 4, PLANES = 1;
+    static constexpr int RB = 16, NACC = 4, PLANES = 1, NMMA = 2;
     using frag = f64x2;
     using acc = f64x4;
     using out_t = double;
@@ -60,7 +62,7 @@ template <> struct MT<P_F64> {
 };
 
 template <> struct MT<P_BF16> {
-    static constexpr int RB = 32, NACC = 16, PLANES = 1;
+    static constexpr int RB = 32, NACC = 16, PLANES = 1, NMMA = 1;
     using frag = bf16x8;
     using acc = f32x16;
     using out_t = float;
@@ -72,7 +74,7 @@ template <> struct MT<P_BF16> {
 };
 
 template <> struct MT<P_BF16X3> {
-    static constexpr int RB = 32, NACC = 16, PLANES = 2;
+    static constexpr int RB = 32, NACC = 16, PLANES = 2, NMMA = 3;
     using frag = bf16x8;
     using acc = f32x16;
     using out_t = float;
@@ -86,7 +88,7 @@ template <> struct MT<P_BF16X3> {
 };
 
 template <> struct MT<P_F16> {
-    static constexpr int RB = 32, NACC = 16, PLANES = 1;
+    static constexpr int RB = 32, NACC = 16, PLANES = 1, NMMA = 1;
     using frag = f16x8;
     using acc = f32x16;
     using out_t = float;
@@ -98,7 +100,7 @@ template <> struct MT<P_F16> {
 };
 
 template <> struct MT<P_F16X3> {
-    static constexpr int RB = 32, NACC = 16, PLANES = 2;
+    static constexpr int RB = 32, NACC = 16, PLANES = 2, NMMA = 3;
     using frag = f16x8;
     using acc = f32x16;
     using out_t = float;
@@ -618,7 +620,7 @@ __device__ __forceinline__ void gemm_tile_dma(
 // set read during step t - 1) run while those reads are in flight.  A slot
 // is refilled right after the barrier that follows its last read, so the
 // copies still run NS - 2 stages ahead of the stage being waited for.
-template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int NS, int KS>
+template <int PREC, int WM, int WN, int WAVES_M, int WAVES_N, int NS, int KS, bool ILV = false>
 __device__ __forceinline__ void gemm_tile_dma_ra(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane,
     const char* __restrict__ Y, int64_t y_nrb, int64_t y_nkb, int64_t y_plane,
@@ -732,6 +734,17 @@ __device__ __forceinline__ void gemm_tile_dma_ra(
         copy(t + NS, d);
         read((d + 1) % NS, (d + 1) & 1);
         mmas(d & 1);
+        if constexpr (ILV) {
+            constexpr int NR = KS * (WM + WN) * PL;
+            constexpr int NM = KS * WM * WN * T::NMMA;
+            __builtin_amdgcn_sched_group_barrier(0x020, PER_W, 0);
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NM / NR, 0);
+            }
+            if constexpr (NM % NR != 0) __builtin_amdgcn_sched_group_barrier(0x008, NM % NR, 0);
+        }
     };
     const int nfull = nst - nst % NS;
     for (int t0 = 0; t0 < nfull; t0 += NS) {
@@ -750,7 +763,10 @@ __device__ __forceinline__ void gemm_tile_dma_ra(
 // Kernel body selector: KIND 0 = direct fragment loads, 1 = LDS-staged with
 // loads two steps ahead, 2 = LDS-staged with loads four steps ahead, 3 = LDS
 // ring filled by direct global-to-LDS copies, 4 = the same ring with the
-// fragments read one step ahead.
+// fragments read one step ahead, 5 = kind 4 with the step's copies issued
+// first and its fragment reads interleaved one by one with its matrix
+// instructions (scheduling groups), so that the LDS command queue never
+// holds a whole step's reads in front of the matrix pipe.
 template <int KIND, int PREC, int WM, int WN, int WAVES_M, int WAVES_N>
 __device__ __forceinline__ void gemm_any(
     const char* __restrict__ X, int64_t x_nrb, int64_t x_nkb, int64_t x_plane, int64_t x_pb,
@@ -758,7 +774,10 @@ __device__ __forceinline__ void gemm_any(
     int64_t nkb, int64_t kb_lo, int64_t P, int64_t Q, typename MT<PREC>::out_t* __restrict__ R, int64_t ldr,
     float beta, int64_t tm, int64_t tn)
 {
-    if constexpr (KIND == 4 && sizeof(typename MT<PREC>::frag) == 16)
+    if constexpr (KIND == 5 && sizeof(typename MT<PREC>::frag) == 16)
+        gemm_tile_dma_ra<PREC, WM, WN, WAVES_M, WAVES_N, 4, gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>(), true>(
+            X, x_nrb, x_nkb, x_plane, Y, y_nrb, y_nkb, y_plane, nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
+    else if constexpr (KIND == 4 && sizeof(typename MT<PREC>::frag) == 16)
         gemm_tile_dma_ra<PREC, WM, WN, WAVES_M, WAVES_N, 4, gemm_lds_ks<PREC, WM, WN, WAVES_M, WAVES_N>()>(
             X, x_nrb, x_nkb, x_plane, Y, y_nrb, y_nkb, y_plane, nkb, kb_lo, P, Q, R, ldr, beta, tm, tn);
     else if constexpr (KIND == 3 && sizeof(typename MT<PREC>::frag) == 16)
@@ -886,7 +905,7 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
 
 }  // namespace
 
-// Tile configurations: (kind: 0 direct fragment loads, 1 - 4 LDS-staged; MFMA
+// Tile configurations: (kind: 0 direct fragment loads, 1 - 5 LDS-staged; MFMA
 // blocks per wave along M, along N; waves along M, along N; minimum resident
 // workgroups per CU).  The workgroup tile is RB*WM*WAVES_M x RB*WN*WAVES_N.
 // FP8 runs the LDS kinds as direct.
@@ -908,7 +927,8 @@ int launch_gemm_t(const GemmArgs& a, hipStream_t s)
     X(14, 3, 4, 2, 2, 2, 1)  \
     X(15, 2, 2, 2, 4, 2, 1)  \
     X(16, 4, 2, 2, 4, 2, 1)  \
-    X(17, 4, 2, 2, 2, 2, 2)
+    X(17, 4, 2, 2, 2, 2, 2)  \
+    X(18, 5, 2, 2, 4, 2, 1)
 
 namespace {
 struct TileCfg { int wm, wn, wavm, wavn; };
@@ -1010,7 +1030,7 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
     case P_F64: return 10;                                 // LDS, 8 waves, 128 x 64 (16 x 16 blocks)
     case P_F32:
         if (!fill256) return 0;
-        return nkb >= 64 ? 16 : 10;                        // long: copy ring read ahead, 256 x 128; else LDS 8 waves
+        return nkb >= 64 ? 18 : 10;                        // long: copy ring read ahead, interleaved; else LDS 8 waves
     case P_FP8:
     case P_FP8X2: return 9;                                // 128 x 256, 8 waves, fragments direct
     case P_BF16X3:

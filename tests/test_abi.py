@@ -49,7 +49,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_tile_configs(lib):
     cfgs = pg.tile_configs("f32")
-    assert len(cfgs) == 18 and (128, 128) in cfgs
+    assert len(cfgs) == 19 and (128, 128) in cfgs
     assert all(m % 32 == 0 and n % 32 == 0 for m, n in cfgs)
     assert all(m % 16 == 0 for m, _ in pg.tile_configs("f64"))
 

@@ -60,7 +60,7 @@ def test_small_uneven_batch(pg, prec, r):
         _tol.assert_within(R.double().cpu().numpy(), ref, _bound(prec, A, B, C, D, r, L), f"problem {i} {prec} r={r}")
 
 
-@pytest.mark.parametrize("cfg", range(18))
+@pytest.mark.parametrize("cfg", range(19))
 def test_every_tile_config_and_layouts(pg, cfg):
     """Each workgroup tile configuration of the persistent launch, with mixed
     layouts: A stored transposed, B stored transposed."""
