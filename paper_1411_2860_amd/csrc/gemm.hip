@@ -1030,7 +1030,7 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
     case P_F64: return 10;                                 // LDS, 8 waves, 128 x 64 (16 x 16 blocks)
     case P_F32:
         if (!fill256) return 0;
-        return nkb >= 64 ? 18 : 10;                        // long: copy ring read ahead, interleaved; else LDS 8 waves
+        return nkb >= 16 ? 18 : 10;                        // copy ring read ahead, interleaved; very short: LDS 8 waves
     case P_FP8:
     case P_FP8X2: return 9;                                // 128 x 256, 8 waves, fragments direct
     case P_BF16X3:
