@@ -190,7 +190,7 @@ def full_images():
     return A, Bt
 
 
-@pytest.mark.parametrize("r", [1, 16, 64])
+@pytest.mark.parametrize("r", [1, 2, 4, 7, 16, 64])
 def test_full_size_sampled(pg, full_images, r):
     """1024 queries x 8192 database images of 64 x 64, L = 64, FP32, in the
     launch configuration the benchmark times; 48 x 48 sampled outputs
@@ -211,6 +211,31 @@ def test_full_size_sampled(pg, full_images, r):
     if r == 64:
         exact = A[rows] @ Bt[cols].T
         assert oracle.rel_fro(got, exact) < 1e-5
+
+
+def test_default_tile_ragged_tail(pg):
+    """An output large enough for the library's 256 x 128 default tile with
+    ragged sides (1000 x 8200) and a contraction of 21 k-blocks (K = 1500,
+    L = 64, r = 7): the ring of four stages ends in a partial trip of three
+    steps, and the last row and column tiles are partly outside.  Sampled
+    outputs (both ends included) against the oracle."""
+    M, W, K, L, r = 1000, 8200, 1500, 64, 7
+    rng = np.random.default_rng(21)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, W))
+    basis = pg.Basis("dct2", L)
+    C, D = _ref.oracle_basis("dct2", L)
+    R = pg.gemm(_dev(A, torch.float32), _dev(B, torch.float32), r, basis)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([[0, 255, 256, M - 1], rng.choice(M, 40, replace=False)]))
+    cols = np.unique(np.concatenate([[0, 127, 128, W - 1], rng.choice(W, 40, replace=False)]))
+    got = R[torch.from_numpy(rows).cuda()][:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
+    A32 = A.astype(np.float32).astype(np.float64)
+    B32 = B.astype(np.float32).astype(np.float64)
+    ref = oracle.gemm_proj_block(A32, B32, C, D, r, rows, cols)
+    mag = oracle.gemm_proj_block(np.abs(A32), np.abs(B32), np.abs(C), np.abs(D), r, rows, cols)
+    Gp = -(-(-(-K // L)) // 8) * 8
+    _tol.assert_within(got, ref, _tol.gemm_bound("f32", L, r, Gp, mag), "default tile, ragged tail")
 
 
 _SAMPLE_REF = {}
