@@ -213,19 +213,21 @@ def test_full_size_sampled(pg, full_images, r):
         assert oracle.rel_fro(got, exact) < 1e-5
 
 
-def test_default_tile_ragged_tail(pg):
-    """An output large enough for the library's 256 x 128 default tile with
-    ragged sides (1000 x 8200) and a contraction of 21 k-blocks (K = 1500,
-    L = 64, r = 7): the ring of four stages ends in a partial trip of three
-    steps, and the last row and column tiles are partly outside.  Sampled
-    outputs (both ends included) against the oracle."""
-    M, W, K, L, r = 1000, 8200, 1500, 64, 7
-    rng = np.random.default_rng(21)
+@pytest.mark.parametrize("prec,K,L,r", [("f32", 1500, 64, 7), ("bf16", 5440, 16, 3), ("bf16x3", 5440, 16, 3)])
+def test_default_tile_ragged_tail(pg, prec, K, L, r):
+    """An output large enough for the library's 256 x 128 default tiles with
+    ragged sides (1000 x 8200) and contractions that end in a partial trip of
+    the four-stage ring: FP32 21 k-blocks (11 steps of 2), BF16 66 k-blocks
+    (33 steps of 2), BF16x3 66 k-blocks (66 steps of 1); the last row and
+    column tiles are partly outside.  Sampled outputs (both ends included)
+    against the oracle."""
+    M, W = 1000, 8200
+    rng = np.random.default_rng(K + r)
     A = rng.standard_normal((M, K))
     B = rng.standard_normal((K, W))
     basis = pg.Basis("dct2", L)
     C, D = _ref.oracle_basis("dct2", L)
-    R = pg.gemm(_dev(A, torch.float32), _dev(B, torch.float32), r, basis)
+    R = pg.gemm(_dev(A, torch.float32), _dev(B, torch.float32), r, basis, prec=prec)
     torch.cuda.synchronize()
     rows = np.unique(np.concatenate([[0, 255, 256, M - 1], rng.choice(M, 40, replace=False)]))
     cols = np.unique(np.concatenate([[0, 127, 128, W - 1], rng.choice(W, 40, replace=False)]))
@@ -234,8 +236,8 @@ def test_default_tile_ragged_tail(pg):
     B32 = B.astype(np.float32).astype(np.float64)
     ref = oracle.gemm_proj_block(A32, B32, C, D, r, rows, cols)
     mag = oracle.gemm_proj_block(np.abs(A32), np.abs(B32), np.abs(C), np.abs(D), r, rows, cols)
-    Gp = -(-(-(-K // L)) // 8) * 8
-    _tol.assert_within(got, ref, _tol.gemm_bound("f32", L, r, Gp, mag), "default tile, ragged tail")
+    Gp = -(-(-(-K // L)) // KB[prec]) * KB[prec]
+    _tol.assert_within(got, ref, _tol.gemm_bound(prec, L, r, Gp, mag), f"default tile, ragged tail, {prec}")
 
 
 _SAMPLE_REF = {}
