@@ -208,6 +208,7 @@ def test_block_rate_paper_operating_points(pg, L, N):
     (513, 64, 1, "identity"),   # L = 1: every output computed
     (4099, 300, 256, "dct2"),   # largest L
     (700, 33, 5, "dct2"),       # L not a power of two
+    (2001, 97, 10, "dct2"),     # L not a multiple of 4: the rebuilt taps pad L and r to 12 (at r = L)
 ])
 def test_block_rate_ragged(pg, W, N, L, kind):
     rng = np.random.default_rng(W + N + 1)
