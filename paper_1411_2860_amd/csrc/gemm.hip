@@ -1037,7 +1037,10 @@ int gemm_default_config(int prec, int64_t P, int64_t Q, int64_t nkb)
     case P_F16X3:
     default:                                               // BF16, FP16 and their x3 splits
         if (!fill256) return 0;                            // direct 128 x 128
-        return nkb >= 64 ? 16 : 9;                         // long: copy ring read ahead, 256 x 128; else LDS 8 waves
+        // copy ring read ahead, 256 x 128: from 64 k-blocks, or from 16 when
+        // those tiles are one round on the chip (with more rounds the shorter
+        // prologue of the LDS-staged 128 x 256 tile wins below 64)
+        return (nkb >= 64 || (nkb >= 16 && cdiv(P, 256) * cdiv(Q, 128) <= 256)) ? 16 : 9;
     }
 }
 
